@@ -1,0 +1,39 @@
+/*
+ * octohydro_oracle.h -- interface of the FP64 CPU oracle (test infrastructure
+ * only; see octohydro_oracle.c).  Independent of the library's public header.
+ */
+#ifndef OCTOHYDRO_ORACLE_H
+#define OCTOHYDRO_ORACLE_H
+
+#include <stdint.h>
+
+#define ORACLE_MAX_NF 16
+
+enum { ORACLE_SAME_LEAF = 0, ORACLE_SAME_REFINED = 1, ORACLE_COARSER_LEAF = 2 };
+enum { ORACLE_OK = 0, ORACLE_E_ARG = -1, ORACLE_E_TABLE = -2 };
+
+typedef struct {
+  int32_t n_leaves, nf, base;
+  const int32_t* coord;    /* [n_leaves][4]: level, ix, iy, iz */
+  const int32_t* nbr;      /* [n_leaves][27] */
+  const uint8_t* kind;     /* [n_leaves][27] */
+  const int32_t* children; /* [n_nodes][8] */
+  double gamma, eta1;
+} ogrid;
+
+int oracle_build_table(int32_t n_leaves, int32_t base, const int32_t* leaf_coord, int32_t* nbr,
+                       uint8_t* kind, int32_t* children, int32_t max_nodes, int32_t* n_nodes_out);
+void oracle_fill_ghosts(const ogrid* g, const double* U, double* G);
+void oracle_ppm_1d(const double* q, int n, double* qL, double* qR);
+int oracle_face_flux(int d, int nf, const double* UL, const double* UR, double gamma, double eta1,
+                     double* H);
+int64_t oracle_step(const ogrid* g, const double* U0, const double* Uk, double* Uout, double dt,
+                    double beta);
+double oracle_cfl_dt(const ogrid* g, const double* U, double cfl);
+void oracle_totals(const ogrid* g, const double* U, double* out);
+int64_t oracle_rk3_step(const ogrid* g, double* U, double* W1, double* W2, double cfl,
+                        double dt_in, double* dt_out);
+int64_t oracle_step_1d(int32_t n, int nf, const double* U0, const double* Uk, double* Uout,
+                       double dt, double beta, double gamma, double eta1);
+
+#endif
