@@ -1,0 +1,206 @@
+/*
+ * octohydro.h -- C-ABI of liboctohydro.so: the hydro step of an octree of
+ * 8^3 sub-grids on one AMD Instinct MI355X (gfx950).
+ *
+ * What the library computes is the per-sub-grid hydro substep of the paper
+ * "Distributed, combined CPU and GPU profiling within HPX using APEX"
+ * (arXiv 2210.06437): the domain is a properly nested octree whose nodes are
+ * N^3 = 8^3 Cartesian sub-grids, each refinable into 8 children at twice the
+ * resolution (Sec. IV-C); every sub-grid fills its ghost cells directly from
+ * its neighbours' memory (Sec. VI); the evolved variables are reconstructed
+ * with PPM and fluxes come from a finite-volume central scheme for the
+ * inviscid Euler equations (Sec. IV-C; kernels "reconstruct" and "flux" in
+ * Sec. V-B-1); each Runge-Kutta substep computes fluxes, takes part in the
+ * global time-step size and updates the variables (Sec. V-B-1,
+ * compute_fluxes); a time step is three hydro substeps (Sec. I).
+ * The paper names these methods only; the library implements the textbook
+ * forms: Colella-Woodward PPM per conserved field, the Kurganov-Tadmor flux at
+ * face centres, Shu-Osher SSP-RK3, an ideal gas with an entropy tracer and a
+ * dual-energy switch.
+ *
+ * Conventions shared by every entry point:
+ *  - Fields, in order: rho, s_x, s_y, s_z, E, tau, then passive species
+ *    rho_0.. (n_fields in [6, 16]).
+ *  - State arrays are structure-of-arrays [n_fields][n_leaves][8][8][8] with x
+ *    fastest, in the element type named by hydro_grid.dtype.  Ghosted tiles
+ *    are [n_fields][n_leaves][14][14][14] (interior at [3,11)^3).
+ *  - The domain is the periodic unit cube; a leaf at level L with coordinates
+ *    (ix,iy,iz) covers level-L cells [8 ix, 8 ix + 8) x ... of width
+ *    1 / (8 base 2^L).
+ *  - All pointers named *_dev are device pointers owned by the caller; they
+ *    must stay valid until the work queued on `stream` has finished.
+ *    `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Calls are asynchronous on `stream` unless stated.  Arguments are
+ *    checked on the host before anything is queued; a failing call queues
+ *    nothing and returns a negative status; hydro_last_error() then gives a
+ *    message (per calling thread).  No C++ exception crosses this boundary.
+ */
+#ifndef OCTOHYDRO_H
+#define OCTOHYDRO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define HYDRO_OK 0
+#define HYDRO_E_ARG (-1)          /* bad argument, caught on the host        */
+#define HYDRO_E_TABLE (-2)        /* inconsistent neighbour table             */
+#define HYDRO_E_UNPHYSICAL (-3)   /* rho <= 0 or p <= 0 met at a face         */
+#define HYDRO_E_HIP (-4)          /* HIP runtime error (message has details)  */
+#define HYDRO_E_UNSUPPORTED (-5)  /* valid request this build does not serve  */
+
+/* element types */
+#define HYDRO_F64 0  /* binary64 storage and arithmetic                       */
+#define HYDRO_F32 1  /* binary32 storage and face arithmetic; flux divergence,
+                        stage combination, totals and time step in binary64  */
+
+/* neighbour kinds in the 27-slot table */
+#define HYDRO_SAME_LEAF 0     /* leaf at the same level: copy                */
+#define HYDRO_SAME_REFINED 1  /* refined node at the same level: mean of the
+                                 8 covering cells of its children            */
+#define HYDRO_COARSER_LEAF 2  /* leaf one level coarser: injection           */
+
+/* status bits written to hydro_grid.status_dev */
+#define HYDRO_STATUS_UNPHYSICAL 1u
+#define HYDRO_STATUS_TABLE 2u
+
+/* flags */
+#define HYDRO_FLAG_VALIDATE 1u  /* check table ids on the device and wait    */
+
+/*
+ * A batch of leaves (Sec. IV-C): host struct, device arrays.
+ *  leaf_coord_dev  int32 [n_leaves][4]: level, ix, iy, iz.
+ *  nbr_dev         int32 [n_leaves][27]: slot (dz+1)*9+(dy+1)*3+(dx+1) of the
+ *                  neighbour in direction (dx,dy,dz); slot 13 is the leaf
+ *                  itself.  A leaf index for SAME_LEAF / COARSER_LEAF, a row
+ *                  of children_dev for SAME_REFINED.  Periodic wrap is folded
+ *                  into the table.
+ *  nbr_kind_dev    uint8 [n_leaves][27]: HYDRO_SAME_LEAF / _SAME_REFINED /
+ *                  _COARSER_LEAF.
+ *  children_dev    int32 [n_nodes][8]: child leaf at (2x+a, 2y+b, 2z+c) in
+ *                  entry c*4+b*2+a, or -1 (children the 3-layer halo never
+ *                  reads may be -1).
+ *  status_dev      int32, or NULL: kernels OR status bits into it.
+ * The tree must be 2:1 balanced over all 26 neighbours ("properly nested").
+ */
+typedef struct hydro_grid {
+  int32_t n_leaves;
+  int32_t n_nodes;
+  int32_t n_fields;
+  int32_t dtype;
+  int32_t base; /* level-0 sub-grids per axis */
+  int32_t reserved;
+  const int32_t* leaf_coord_dev;
+  const int32_t* nbr_dev;
+  const uint8_t* nbr_kind_dev;
+  const int32_t* children_dev;
+  int32_t* status_dev;
+  double gamma;            /* ratio of specific heats, e.g. 5.0/3.0        */
+  double dual_energy_eta1; /* internal energy from tau when e < eta1 E;
+                              <= 0 disables the switch                       */
+} hydro_grid;
+
+/*
+ * Neighbour table of a leaf list (Sec. IV-C octree), on the host.
+ * leaf_coord: host int32 [n_leaves][4]; outputs nbr [n_leaves][27],
+ * kind [n_leaves][27] and children [max_nodes][8] (host, caller-owned).
+ * Refined nodes are numbered in order of first reference (leaves ascending,
+ * slots ascending).  Returns HYDRO_E_TABLE for duplicate leaves, a leaf that
+ * two levels separate from a neighbour, or more than max_nodes refined
+ * neighbours.  Synchronous, host only; touches no GPU.
+ */
+int hydro_build_table(int32_t n_leaves, int32_t base, const int32_t* leaf_coord,
+                      int32_t* nbr, uint8_t* kind, int32_t* children,
+                      int32_t max_nodes, int32_t* n_nodes_out);
+
+/*
+ * Ghost fill (Sec. VI: neighbours read directly, no message buffers): writes
+ * every cell of the ghosted tiles G_dev [nf][n][14][14][14] from U_dev
+ * [nf][n][8][8][8] -- interior copy, same-level copy, injection from a
+ * coarser leaf, or the mean of 8 finer cells, summed as
+ * ((v000+v100)+(v010+v110)) + ((v001+v101)+(v011+v111)) times 0.125.
+ * Bit-exact integer/index work; G_dev must not overlap U_dev.
+ */
+int hydro_fill_ghosts(const hydro_grid* grid, const void* U_dev, void* G_dev, void* stream);
+
+/*
+ * One Runge-Kutta substep over all leaves (Sec. V-B-1, compute_fluxes):
+ * t = Uk + dt * L(Uk) with L the negative flux divergence from PPM face
+ * states and the Kurganov-Tadmor flux, then
+ *   Uout = t                       if U0_dev == NULL,
+ *   Uout = U0 + beta * (t - U0)    otherwise.
+ * The ghost fill is fused: each sub-grid reads its neighbours' cells
+ * directly.  dt is read on the device from *dt_dev (binary64).
+ * Uout_dev may alias neither Uk_dev nor U0_dev.  flags: HYDRO_FLAG_VALIDATE.
+ */
+int hydro_step(const hydro_grid* grid, const void* U0_dev, const void* Uk_dev, void* Uout_dev,
+               const double* dt_dev, double beta, uint32_t flags, void* stream);
+
+/*
+ * Same substep, launched once per leaf round-robin over a pool of n_streams
+ * HIP streams owned by the library (the paper's one-kernel-per-sub-grid
+ * design with a pool of 128 streams, Sec. IV-C).  Ordered after earlier work
+ * on `stream`, and later work on `stream` waits for all of it.  For
+ * comparison with hydro_step; results are bit-identical to it.
+ */
+int hydro_step_per_leaf(const hydro_grid* grid, const void* U0_dev, const void* Uk_dev,
+                        void* Uout_dev, const double* dt_dev, double beta, int32_t n_streams,
+                        void* stream);
+
+/*
+ * Global time-step size (Sec. V-B-1): *dt_dev = cfl * min over all leaves and
+ * interior cells of dx_L / (max(|v_x|,|v_y|,|v_z|) + c), in binary64 for
+ * either dtype.  Exact min reduction: the result does not depend on order.
+ */
+int hydro_cfl_dt(const hydro_grid* grid, const void* U_dev, double cfl, double* dt_dev,
+                 void* stream);
+
+/*
+ * Conserved totals: totals_dev[f] = sum over cells of U_f * dx_L^3, binary64
+ * with double-double (TwoSum) accumulation.  Uses a library-owned scratch
+ * buffer (allocated on first use per device).
+ */
+int hydro_totals(const hydro_grid* grid, const void* U_dev, double* totals_dev, void* stream);
+
+/*
+ * One SSP-RK3 time step (three substeps, Sec. I):
+ *   if cfl > 0: *dt_dev = hydro_cfl_dt(Un);  else *dt_dev is used as given;
+ *   W1 = Un + dt L(Un);  W2 = Un + 1/4 (W1 + dt L(W1) - Un);
+ *   Unext = Un + 2/3 (W2 + dt L(W2) - Un).
+ * W1_dev, W2_dev are caller scratch of the state's size; Unext_dev may be
+ * W1_dev but not Un_dev or W2_dev.
+ */
+int hydro_rk3_step(const hydro_grid* grid, const void* Un_dev, void* W1_dev, void* W2_dev,
+                   void* Unext_dev, double cfl, double* dt_dev, void* stream);
+
+/*
+ * The same RK3 step captured once into a HIP graph (argument values and
+ * pointers are frozen at capture).  hydro_graph_launch replays it on
+ * `stream`; hydro_graph_destroy frees it.  *graph_out is an opaque handle.
+ */
+int hydro_rk3_graph_create(const hydro_grid* grid, const void* Un_dev, void* W1_dev,
+                           void* W2_dev, void* Unext_dev, double cfl, double* dt_dev,
+                           void** graph_out);
+int hydro_graph_launch(void* graph, void* stream);
+int hydro_graph_destroy(void* graph);
+
+/*
+ * Waits for `stream`, then reads grid->status_dev: returns HYDRO_OK,
+ * HYDRO_E_UNPHYSICAL or HYDRO_E_TABLE.  Synchronous.
+ */
+int hydro_check_status(const hydro_grid* grid, void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* hydro_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int hydro_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCTOHYDRO_H */

@@ -77,6 +77,8 @@ def _load():
     lib.oracle_face_flux.restype = ctypes.c_int
     lib.oracle_step.argtypes = [ctypes.POINTER(_OGrid), vp, vp, vp, f64, f64]
     lib.oracle_step.restype = ctypes.c_int64
+    lib.oracle_step_subset.argtypes = [ctypes.POINTER(_OGrid), vp, vp, vp, f64, f64, vp, i32]
+    lib.oracle_step_subset.restype = ctypes.c_int64
     lib.oracle_cfl_dt.argtypes = [ctypes.POINTER(_OGrid), vp, f64]
     lib.oracle_cfl_dt.restype = f64
     lib.oracle_totals.argtypes = [ctypes.POINTER(_OGrid), vp, vp]
@@ -182,6 +184,34 @@ def step(table: Table, Uk, dt, beta=1.0, U0=None, gamma=GAMMA, eta1=ETA1):
     bad = _load().oracle_step(ctypes.byref(_grid(table, nf, gamma, eta1)), _ptr(U0), _ptr(Uk),
                               _ptr(out), float(dt), float(beta))
     return out, bad
+
+
+def step_subset(table: Table, Uk, dt, leaves, beta=1.0, U0=None, out=None, gamma=GAMMA,
+                eta1=ETA1):
+    """The substep of :func:`step` computed only for `leaves`; other leaves of
+    `out` keep their values (NaN when `out` is not given)."""
+    Uk = _c64(Uk)
+    U0 = None if U0 is None else _c64(U0)
+    leaves = np.ascontiguousarray(leaves, dtype=np.int32)
+    if out is None:
+        out = np.full_like(Uk, np.nan)
+    bad = _load().oracle_step_subset(ctypes.byref(_grid(table, Uk.shape[0], gamma, eta1)),
+                                     _ptr(U0), _ptr(Uk), _ptr(out), float(dt), float(beta),
+                                     _ptr(leaves), len(leaves))
+    return out, bad
+
+
+def neighbours(table: Table, leaves):
+    """Leaves whose cells the ghost fill of `leaves` reads, plus `leaves`."""
+    out = set(int(x) for x in leaves)
+    for n in leaves:
+        for s in range(27):
+            k, m = int(table.kind[n, s]), int(table.nbr[n, s])
+            if k == SAME_REFINED:
+                out.update(int(c) for c in table.children[m] if c >= 0)
+            else:
+                out.add(m)
+    return np.array(sorted(out), dtype=np.int32)
 
 
 def cfl_dt(table: Table, U, cfl, gamma=GAMMA, eta1=ETA1):

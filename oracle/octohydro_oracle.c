@@ -357,9 +357,10 @@ static void combine(int has_u0, double beta, double dt, double u0, double uk, do
   *out = has_u0 ? u0 + beta * (t - u0) : t;
 }
 
-int64_t oracle_step(const ogrid* g, const double* U0, const double* Uk, double* Uout, double dt,
-                    double beta) {
+int64_t oracle_step_subset(const ogrid* g, const double* U0, const double* Uk, double* Uout,
+                           double dt, double beta, const int32_t* subset, int32_t n_subset) {
   const int nf = g->nf;
+  const int32_t n_work = subset ? n_subset : g->n_leaves;
   int64_t bad_total = 0;
 #pragma omp parallel reduction(+ : bad_total)
   {
@@ -368,7 +369,8 @@ int64_t oracle_step(const ogrid* g, const double* U0, const double* Uk, double* 
     double pen[ORACLE_MAX_NF][TW], pL[ORACLE_MAX_NF][TW], pR[ORACLE_MAX_NF][TW];
     double UL[ORACLE_MAX_NF], UR[ORACLE_MAX_NF], H[TW][ORACLE_MAX_NF];
 #pragma omp for schedule(dynamic, 4)
-    for (int32_t n = 0; n < g->n_leaves; ++n) {
+    for (int32_t w = 0; w < n_work; ++w) {
+      const int32_t n = subset ? subset[w] : w;
       const int32_t L = g->coord[4 * n + 0];
       const double inv_dx = (double)(SUB * (g->base << L));
       for (int f = 0; f < nf; ++f)
@@ -421,6 +423,11 @@ int64_t oracle_step(const ogrid* g, const double* U0, const double* Uk, double* 
     free(dH);
   }
   return bad_total;
+}
+
+int64_t oracle_step(const ogrid* g, const double* U0, const double* Uk, double* Uout, double dt,
+                    double beta) {
+  return oracle_step_subset(g, U0, Uk, Uout, dt, beta, NULL, 0);
 }
 
 /* ------------------------------------------------------------------------ */

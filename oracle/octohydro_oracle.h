@@ -29,6 +29,10 @@ int oracle_face_flux(int d, int nf, const double* UL, const double* UR, double g
                      double* H);
 int64_t oracle_step(const ogrid* g, const double* U0, const double* Uk, double* Uout, double dt,
                     double beta);
+/* Same substep, computed only for the leaves listed in subset (Uout of the
+ * other leaves is left untouched). */
+int64_t oracle_step_subset(const ogrid* g, const double* U0, const double* Uk, double* Uout,
+                           double dt, double beta, const int32_t* subset, int32_t n_subset);
 double oracle_cfl_dt(const ogrid* g, const double* U, double cfl);
 void oracle_totals(const ogrid* g, const double* U, double* out);
 int64_t oracle_rk3_step(const ogrid* g, double* U, double* W1, double* W2, double cfl,

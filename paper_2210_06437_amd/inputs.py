@@ -302,7 +302,7 @@ def turbulence(base: int = 32, n_refine: int = 4681, seed_offset: int = 5,
     for i, Kc in enumerate((KX, KY, KZ)):
         what[i] = what[i] - Kc * kdotw / K2s
     del kdotw, K2s
-    v = [np.fft.irfftn(w, s=(N, N, N)) for w in what]
+    v = [np.fft.irfftn(w, s=(N, N, N), axes=(0, 1, 2)) for w in what]
     del what
     vrms = np.sqrt((v[0] ** 2 + v[1] ** 2 + v[2] ** 2).mean())
     scale = mach * np.sqrt(GAMMA) / vrms

@@ -1,0 +1,143 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library loads, exports every symbol the public header declares, builds
+neighbour tables identical to the oracle's, and rejects bad arguments on the
+host before queueing any GPU work.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_06437_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "octohydro.h")
+
+
+@pytest.fixture(scope="module")
+def hb():
+    from paper_2210_06437_amd import binding
+    return binding
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hydro_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(hb):
+    names = _declared()
+    assert len(names) >= 12
+    lib = ctypes.CDLL(hb.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(hb.EXPORTS)
+    assert hb.hydro_version() >= 100
+
+
+def _trees():
+    yield inputs.uniform_leaves(1), 1
+    yield inputs.uniform_leaves(3), 3
+    w = inputs.blobs(base=2, max_level=2, threshold=0.5)
+    yield w.leaf_coord, w.base
+    w = inputs.blobs(base=4, max_level=3, threshold=0.05)
+    yield w.leaf_coord, w.base
+
+
+@pytest.mark.parametrize("which", range(4))
+def test_table_bit_exact_vs_oracle(hb, which):
+    coord, base = list(_trees())[which]
+    nbr, kind, kids = hb.hydro_build_table(coord, base)
+    T = oracle.Table(coord, base)
+    assert np.array_equal(nbr, T.nbr)
+    assert np.array_equal(kind, T.kind)
+    assert kids.shape[0] == T.n_nodes
+    if T.n_nodes:
+        assert np.array_equal(kids, T.children[: T.n_nodes])
+
+
+def test_table_bit_exact_on_the_uneven_octree_workload(hb):
+    w = inputs.config3()
+    nbr, kind, kids = hb.hydro_build_table(w.leaf_coord, w.base)
+    T = oracle.Table(w.leaf_coord, w.base)
+    assert np.array_equal(nbr, T.nbr) and np.array_equal(kind, T.kind)
+    assert np.array_equal(kids, T.children[: T.n_nodes])
+    assert set(np.unique(kind).tolist()) == {0, 1, 2}
+
+
+def test_table_rejects_bad_trees(hb):
+    base = 2
+    leaves = set(map(tuple, inputs.uniform_leaves(base).tolist()))
+    leaves.discard((0, 0, 0, 0))
+    for q in range(8):
+        leaves.add((1, q & 1, (q >> 1) & 1, q >> 2))
+    leaves.discard((1, 1, 1, 1))
+    for q in range(8):
+        leaves.add((2, 2 + (q & 1), 2 + ((q >> 1) & 1), 2 + (q >> 2)))
+    c = np.array(sorted(leaves), np.int32)
+    with pytest.raises(hb.HydroError) as e:
+        hb.hydro_build_table(c, base)
+    assert e.value.code == hb.HYDRO_E_TABLE
+    dup = np.concatenate([inputs.uniform_leaves(2), inputs.uniform_leaves(2)[:1]])
+    with pytest.raises(hb.HydroError) as e:
+        hb.hydro_build_table(dup, 2)
+    assert e.value.code == hb.HYDRO_E_TABLE
+    bad = inputs.uniform_leaves(2).copy()
+    bad[0, 1] = 5
+    with pytest.raises(hb.HydroError) as e:
+        hb.hydro_build_table(bad, 2)
+    assert e.value.code == hb.HYDRO_E_ARG
+
+
+def _raw_grid(hb, **kw):
+    g = hb.hydro_grid(n_leaves=8, n_nodes=0, n_fields=6, dtype=0, base=2, reserved=0,
+                      leaf_coord_dev=16, nbr_dev=16, nbr_kind_dev=16, children_dev=None,
+                      status_dev=None, gamma=5.0 / 3.0, dual_energy_eta1=1e-3)
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+@pytest.mark.parametrize("field,value", [("n_leaves", 0), ("n_fields", 5), ("n_fields", 17),
+                                         ("dtype", 7), ("base", 0), ("gamma", 1.0),
+                                         ("nbr_dev", None)])
+def test_entry_points_reject_bad_grids_on_the_host(hb, field, value):
+    lib = hb._lib
+    g = _raw_grid(hb, **{field: value})
+    p = ctypes.c_void_p(64)
+    assert lib.hydro_step(ctypes.byref(g), None, p, ctypes.c_void_p(128), p, 1.0, 0,
+                          None) == hb.HYDRO_E_ARG
+    assert lib.hydro_fill_ghosts(ctypes.byref(g), p, ctypes.c_void_p(128), None) == hb.HYDRO_E_ARG
+    assert lib.hydro_cfl_dt(ctypes.byref(g), p, 0.4, p, None) == hb.HYDRO_E_ARG
+    assert hb.hydro_last_error()
+
+
+def test_step_rejects_aliasing_and_flags_on_the_host(hb):
+    lib = hb._lib
+    g = _raw_grid(hb)
+    a, b = ctypes.c_void_p(64), ctypes.c_void_p(128)
+    assert lib.hydro_step(ctypes.byref(g), None, a, a, b, 1.0, 0, None) == hb.HYDRO_E_ARG
+    assert "alias" in hb.hydro_last_error()
+    assert lib.hydro_step(ctypes.byref(g), b, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
+    assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 8, None) == hb.HYDRO_E_ARG
+    assert lib.hydro_step(None, None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
+    g12 = _raw_grid(hb, n_fields=12)
+    assert lib.hydro_step(ctypes.byref(g12), None, a, b, a, 1.0, 0,
+                          None) == hb.HYDRO_E_UNSUPPORTED
+    assert lib.hydro_rk3_step(ctypes.byref(g), a, b, b, a, 0.4, a, None) == hb.HYDRO_E_ARG
+    assert lib.hydro_graph_launch(None, None) == hb.HYDRO_E_ARG
+    assert lib.hydro_check_status(ctypes.byref(g), None) == hb.HYDRO_E_ARG
+
+
+def test_product_path_has_no_oracle_dependency():
+    pkg = os.path.join(ROOT, "paper_2210_06437_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "octohydro_oracle" not in text, f

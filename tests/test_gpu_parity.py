@@ -1,0 +1,319 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle.
+
+Binary64: results must agree within 1e-12 relative per field (max-norm of the
+difference over max-norm of the oracle field); the ghost fill, the table and
+the time step are compared bit for bit.  Binary32 storage: per-field L1 error
+against the FP64 oracle is bounded and reported.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_06437_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    from paper_2210_06437_amd import binding as hb
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, hb
+
+
+def _rel(a, b):
+    nf = b.shape[0]
+    d = np.abs(a - b).reshape(nf, -1).max(1)
+    s = np.abs(b).reshape(nf, -1).max(1)
+    return d / np.maximum(s, 1e-300)
+
+
+def _setup(env, w, dtype=0):
+    torch, hb = env
+    grid = hb.Grid(w.leaf_coord, w.base, w.nf, dtype)
+    T = oracle.Table(w.leaf_coord, w.base)
+    tdt = torch.float64 if dtype == 0 else torch.float32
+    U = torch.from_numpy(w.U).to("cuda").to(tdt).contiguous()
+    return grid, T, U
+
+
+def _small_cases():
+    yield "uniform-base2-nf6", inputs.random_smooth(inputs.uniform_leaves(2), 2, nf=6, seed=1)
+    yield "config1-single-leaf", inputs.config1()
+    yield "amr-base2-levels0-2-nf11", inputs.blobs(base=2, max_level=2, threshold=0.5)
+    yield "amr-base4-levels0-3-nf11", inputs.blobs(base=4, max_level=3)
+    yield "sod-base4", inputs.sod(base=4)
+    tw = inputs.turbulence(base=4, n_refine=9, seed_offset=50)
+    yield "turbulence-base4-refined", tw
+
+
+SMALL = list(_small_cases())
+
+
+@pytest.mark.parametrize("name,w", SMALL, ids=[c[0] for c in SMALL])
+def test_fill_ghosts_bit_exact(env, name, w):
+    torch, hb = env
+    print(f"case {name}: {w.n_leaves} leaves nf={w.nf}", flush=True)
+    grid, T, U = _setup(env, w)
+    G = torch.empty((w.nf, w.n_leaves, 14, 14, 14), dtype=torch.float64, device="cuda")
+    hb.hydro_fill_ghosts(grid, U, G)
+    torch.cuda.synchronize()
+    assert np.array_equal(G.cpu().numpy(), oracle.fill_ghosts(T, w.U))
+
+
+@pytest.mark.parametrize("name,w", SMALL, ids=[c[0] for c in SMALL])
+def test_cfl_dt_bit_exact(env, name, w):
+    torch, hb = env
+    grid, T, U = _setup(env, w)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hb.hydro_cfl_dt(grid, U, 0.4, dt)
+    assert dt.item() == oracle.cfl_dt(T, w.U, 0.4)
+
+
+@pytest.mark.parametrize("name,w", SMALL, ids=[c[0] for c in SMALL])
+def test_substep_f64_matches_oracle(env, name, w):
+    torch, hb = env
+    print(f"case {name}: {w.n_leaves} leaves nf={w.nf}", flush=True)
+    grid, T, U = _setup(env, w)
+    dt_o = oracle.cfl_dt(T, w.U, 0.4)
+    dt = torch.tensor([dt_o], dtype=torch.float64, device="cuda")
+    # first stage (no U0) and a later stage (with U0 and beta)
+    out = grid.empty_state()
+    hb.hydro_step(grid, None, U, out, dt, 1.0)
+    ref, bad = oracle.step(T, w.U, dt_o)
+    assert bad == 0
+    got = out.cpu().numpy()
+    err = _rel(got, ref)
+    print(f"  stage1 rel err per field {err.max():.3e}, bit-exact {np.array_equal(got, ref)}")
+    assert np.all(err <= TOL64), err
+    U0 = torch.from_numpy(ref).to("cuda")
+    out2 = grid.empty_state()
+    hb.hydro_step(grid, U0, U, out2, dt, 0.25)
+    ref2, _ = oracle.step(T, w.U, dt_o, beta=0.25, U0=ref)
+    err2 = _rel(out2.cpu().numpy(), ref2)
+    assert np.all(err2 <= TOL64), err2
+    assert hb.hydro_check_status(grid) == hb.HYDRO_OK
+
+
+@pytest.mark.parametrize("name,w", SMALL[2:5], ids=[c[0] for c in SMALL[2:5]])
+def test_rk3_f64_matches_oracle(env, name, w):
+    torch, hb = env
+    grid, T, U = _setup(env, w)
+    W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Uo = w.U
+    for step in range(3):
+        hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.4, dt)
+        Uo, dto, bad = oracle.rk3_step(T, Uo, 0.4)
+        assert bad == 0
+        assert dt.item() == dto
+        got = Un.cpu().numpy()
+        err = _rel(got, Uo)
+        print(f"  step {step} rel err {err.max():.3e} bit-exact {np.array_equal(got, Uo)}")
+        assert np.all(err <= TOL64), err
+        U, Un = Un, U
+
+
+def test_per_leaf_launches_equal_the_batched_kernel(env):
+    torch, hb = env
+    w = inputs.blobs(base=4, max_level=3)
+    grid, T, U = _setup(env, w)
+    dt = torch.tensor([1e-4], dtype=torch.float64, device="cuda")
+    a, b = grid.empty_state(), grid.empty_state()
+    hb.hydro_step(grid, None, U, a, dt, 1.0)
+    hb.hydro_step_per_leaf(grid, None, U, b, dt, 1.0, n_streams=128)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_graph_replays_match_eager(env):
+    torch, hb = env
+    w = inputs.sod(base=4)
+    grid, T, U = _setup(env, w)
+    W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.4, dt)
+    eager = Un.clone()
+    eager_dt = dt.clone()
+    g = hb.Rk3Graph(grid, U, W1, W2, Un, 0.4, dt)
+    for rep in range(4):
+        Un.fill_(float("nan"))
+        W1.fill_(0.0)
+        dt.fill_(-1.0)
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(Un, eager), rep
+        assert torch.equal(dt, eager_dt), rep
+        _ = (U * 2.0).sum().item()  # unrelated eager work between replays
+    g.close()
+
+
+def test_totals_match_oracle(env):
+    torch, hb = env
+    for w in (inputs.blobs(base=4, max_level=3), inputs.sod(base=4)):
+        grid, T, U = _setup(env, w)
+        out = torch.zeros(w.nf, dtype=torch.float64, device="cuda")
+        hb.hydro_totals(grid, U, out)
+        ref = oracle.totals(T, w.U)
+        scale = oracle.totals(T, np.abs(w.U))
+        assert np.all(np.abs(out.cpu().numpy() - ref) <= 1e-14 * scale)
+
+
+def test_unphysical_state_sets_status(env):
+    torch, hb = env
+    w = inputs.sod(base=2)
+    U = w.U.copy()
+    U[0, 3, 4, 4, 4] = -1.0
+    w.U = U
+    grid, T, Ud = _setup(env, w)
+    dt = torch.tensor([1e-4], dtype=torch.float64, device="cuda")
+    out = grid.empty_state()
+    hb.hydro_step(grid, None, Ud, out, dt, 1.0)
+    assert hb.hydro_check_status(grid) == hb.HYDRO_E_UNPHYSICAL
+    _, bad = oracle.step(T, U, 1e-4)
+    assert bad > 0
+
+
+def test_validate_flag_rejects_a_corrupt_table_before_launch(env):
+    torch, hb = env
+    w = inputs.sod(base=2)
+    grid, T, U = _setup(env, w)
+    grid.nbr[3, 14] = w.n_leaves + 5  # out of range: must never reach the step kernel
+    dt = torch.tensor([1e-4], dtype=torch.float64, device="cuda")
+    out = grid.empty_state()
+    with pytest.raises(hb.HydroError) as e:
+        hb.hydro_step(grid, None, U, out, dt, 1.0, flags=hb.HYDRO_FLAG_VALIDATE)
+    assert e.value.code == hb.HYDRO_E_TABLE
+
+
+def test_fp32_mixed_l1_error_against_fp64_oracle(env):
+    torch, hb = env
+    w = inputs.sod(base=4, steps=10)
+    grid, T, U = _setup(env, w, dtype=1)
+    W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
+    # both sides advance with the oracle's first time step (cfl <= 0: the
+    # device reads dt as given)
+    dt0 = oracle.cfl_dt(T, w.U, 0.4)
+    dt = torch.tensor([dt0], dtype=torch.float64, device="cuda")
+    Uo = w.U
+    tot0 = oracle.totals(T, w.U)
+    tg = torch.zeros(w.nf, dtype=torch.float64, device="cuda")
+    d32 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hb.hydro_cfl_dt(grid, U, 0.4, d32)
+    assert abs(d32.item() - dt0) <= 1e-6 * dt0
+    for _ in range(10):
+        hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.0, dt)
+        Uo, _, _ = oracle.rk3_step(T, Uo, 0.0, dt=dt0)
+        U, Un = Un, U
+    got = U.double().cpu().numpy()
+    l1 = np.abs(got - Uo).reshape(w.nf, -1).sum(1) / np.abs(Uo).reshape(w.nf, -1).sum(1)
+    print("FP32-mixed per-field L1 after 10 RK3 steps:", " ".join(f"{x:.2e}" for x in l1))
+    # rho, E, tau and s_x carry the Sod waves; s_y, s_z are noise of 1e-4
+    assert np.all(l1[[0, 1, 4, 5]] < 1e-5), l1
+    hb.hydro_totals(grid, U, tg)
+    drift = np.abs(tg.cpu().numpy() - tot0) / np.maximum(oracle.totals(T, np.abs(w.U)), 1e-300)
+    print("FP32-mixed total drift (rho, E):", drift[0], drift[4])
+    assert drift[0] < 1e-6 and drift[4] < 1e-6
+
+
+# -- full-size workloads ----------------------------------------------------
+
+def test_sod_128cubed_matches_oracle_and_exact_solution(env):
+    """Sod tube on 16^3 sub-grids (128^3 cells), 10 RK3 steps at CFL 0.4: the
+    first step element by element against the oracle, the final y,z-averaged
+    profile against the exact Riemann solution, totals conserved."""
+    import exact_riemann as er
+    torch, hb = env
+    w = inputs.config2()
+    grid, T, U = _setup(env, w)
+    W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tot0 = torch.zeros(6, dtype=torch.float64, device="cuda")
+    hb.hydro_totals(grid, U, tot0)
+    hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.4, dt)
+    ref, dto, bad = oracle.rk3_step(T, w.U, 0.4)
+    assert dt.item() == dto and bad == 0
+    err = _rel(Un.cpu().numpy(), ref)
+    print(f"config2 step 1 rel err {err.max():.3e}")
+    assert np.all(err <= TOL64), err
+    t = dto
+    U, Un = Un, U
+    for _ in range(9):
+        hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.4, dt)
+        t += dt.item()
+        U, Un = Un, U
+    assert hb.hydro_check_status(grid) == hb.HYDRO_OK
+    tot = torch.zeros(6, dtype=torch.float64, device="cuda")
+    hb.hydro_totals(grid, U, tot)
+    # scale: sum of |q| dV over the larger of the initial and final states
+    # (s_x starts at zero in a Sod tube)
+    dv = (1.0 / 128) ** 3
+    big = np.maximum(np.abs(w.U), np.abs(U.cpu().numpy()))
+    scale = big.reshape(6, -1).sum(1) * dv
+    cons = np.abs(tot.cpu().numpy() - tot0.cpu().numpy()) / scale
+    print("config2 conservation after 10 steps:", cons)
+    assert np.all(cons <= 1e-13)
+    # profile along x
+    rho = U[0].cpu().numpy()
+    N = 128
+    prof = np.zeros(N)
+    for i, (_, x, y, z) in enumerate(w.leaf_coord):
+        prof[8 * x:8 * x + 8] += rho[i].sum(axis=(0, 1))
+    prof /= N * N
+    xc = (np.arange(N) + 0.5) / N
+    ex, _, _ = er.sample(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 5.0 / 3.0, (xc - 0.5) / t)
+    win = (xc > 0.25) & (xc < 0.75)
+    l1 = np.abs(prof - ex)[win].mean()
+    print(f"config2 t={t:.5f} L1(rho) vs exact {l1:.3e}")
+    assert l1 < 0.02
+    assert 0.014 < t < 0.03
+
+
+def _sampled_rk3(env, w, n_samples, seed):
+    """One graph-captured RK3 step on the GPU; the oracle evaluates the three
+    stages only where the sampled leaves' results depend on them."""
+    torch, hb = env
+    grid, T, U = _setup(env, w)
+    W1, W2 = grid.empty_state(), grid.empty_state()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = hb.Rk3Graph(grid, U, W1, W2, W1, 0.4, dt)  # Unext aliases W1
+    g.launch()
+    torch.cuda.synchronize()
+    assert hb.hydro_check_status(grid) == hb.HYDRO_OK
+    rng = np.random.default_rng(seed)
+    lev = w.leaf_coord[:, 0]
+    picks = list(rng.choice(w.n_leaves, n_samples, replace=False))
+    for L in np.unique(lev):  # every level is represented
+        picks.append(int(rng.choice(np.nonzero(lev == L)[0])))
+    S = np.unique(np.array(picks, np.int32))
+    R1 = oracle.neighbours(T, S)
+    R2 = oracle.neighbours(T, R1)
+    dto = oracle.cfl_dt(T, w.U, 0.4)
+    assert dt.item() == dto
+    o1, b1 = oracle.step_subset(T, w.U, dto, R2)
+    o2, b2 = oracle.step_subset(T, o1, dto, R1, beta=0.25, U0=w.U)
+    o3, b3 = oracle.step_subset(T, o2, dto, S, beta=2.0 / 3.0, U0=w.U)
+    assert b1 == b2 == b3 == 0
+    got = W1.cpu().numpy()[:, S]
+    want = o3[:, S]
+    err = _rel(got, want)
+    print(f"{w.n_leaves} leaves: {len(S)} sampled leaves (rings {len(R1)}, {len(R2)}), "
+          f"rel err {err.max():.3e}, bit-exact {np.array_equal(got, want)}")
+    assert np.all(err <= TOL64), err
+    g.close()
+    return grid
+
+
+def test_uneven_octree_22k_leaves_sampled(env):
+    _sampled_rk3(env, inputs.config3(), 48, 3)
+
+
+def test_turbulence_65k_leaves_sampled(env):
+    w = inputs.config5()
+    _sampled_rk3(env, w, 32, 5)
