@@ -88,8 +88,15 @@ def _load():
     lib.oracle_rk3_step.restype = ctypes.c_int64
     lib.oracle_step_1d.argtypes = [i32, ctypes.c_int, vp, vp, vp, f64, f64, f64, f64]
     lib.oracle_step_1d.restype = ctypes.c_int64
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return _load().oracle_num_threads()
 
 
 def _ptr(a):

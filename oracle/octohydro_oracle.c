@@ -34,6 +34,7 @@
  * G[nf][n_leaves][14][14][14]; interior of a tile at [3,11)^3.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -547,3 +548,6 @@ int64_t oracle_step_1d(int32_t n, int nf, const double* U0, const double* Uk, do
   free(H);
   return bad;
 }
+
+/* Threads an OpenMP parallel region of the oracle uses. */
+int oracle_num_threads(void) { return omp_get_max_threads(); }

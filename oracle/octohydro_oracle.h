@@ -40,4 +40,6 @@ int64_t oracle_rk3_step(const ogrid* g, double* U, double* W1, double* W2, doubl
 int64_t oracle_step_1d(int32_t n, int nf, const double* U0, const double* Uk, double* Uout,
                        double dt, double beta, double gamma, double eta1);
 
+int oracle_num_threads(void);
+
 #endif
