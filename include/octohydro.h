@@ -196,6 +196,22 @@ int hydro_check_status(const hydro_grid* grid, void* stream);
 /* Message of the last failing call on this thread ("" if none). */
 const char* hydro_last_error(void);
 
+/*
+ * Launch options of the fused substep kernel for one (dtype, n_fields) pair;
+ * the defaults are 1 wave per SIMD and the XCD remap on.  The autotuner
+ * (paper_2210_06437_amd/autotune.py) times the choices and records the
+ * fastest; the Python binding applies its recorded choices at import.
+ *   HYDRO_OPT_WAVES_PER_SIMD  1 or 2: register budget of the kernel (2 waves
+ *                             per SIMD caps it at 256 VGPRs, which may spill)
+ *   HYDRO_OPT_XCD_REMAP       0 or 1: give each XCD a contiguous leaf range
+ * Options are process-wide and take effect at the next launch (a captured
+ * graph keeps the kernel it was captured with).  Host only, thread-safe.
+ */
+#define HYDRO_OPT_WAVES_PER_SIMD 1
+#define HYDRO_OPT_XCD_REMAP 2
+int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t value);
+int hydro_get_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t* value);
+
 /* Library version, major*10000 + minor*100 + patch. */
 int hydro_version(void);
 

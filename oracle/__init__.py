@@ -88,6 +88,13 @@ def _load():
     lib.oracle_rk3_step.restype = ctypes.c_int64
     lib.oracle_step_1d.argtypes = [i32, ctypes.c_int, vp, vp, vp, f64, f64, f64, f64]
     lib.oracle_step_1d.restype = ctypes.c_int64
+    lib.oracle_step_record.argtypes = [ctypes.POINTER(_OGrid), vp, vp, vp, f64, f64, vp, i32, vp]
+    lib.oracle_step_record.restype = ctypes.c_int64
+    lib.oracle_reflux.argtypes = [ctypes.POINTER(_OGrid), vp, f64, f64, vp, vp, i32]
+    lib.oracle_reflux.restype = None
+    lib.oracle_rk3_step_reflux.argtypes = [ctypes.POINTER(_OGrid), vp, vp, vp, f64, f64,
+                                           ctypes.POINTER(f64), ctypes.c_int]
+    lib.oracle_rk3_step_reflux.restype = ctypes.c_int64
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -234,15 +241,44 @@ def totals(table: Table, U):
     return out
 
 
-def rk3_step(table: Table, U, cfl=0.4, dt=0.0, gamma=GAMMA, eta1=ETA1):
-    """One SSP-RK3 step (three substeps, Sec. I). Returns (U_next, dt, n_bad)."""
+def rk3_step(table: Table, U, cfl=0.4, dt=0.0, gamma=GAMMA, eta1=ETA1, reflux=False):
+    """One SSP-RK3 step (three substeps, Sec. I), optionally with the
+    coarse-fine flux correction after each substep. Returns (U_next, dt, n_bad)."""
     U = _c64(U).copy()
     W1 = np.empty_like(U)
     W2 = np.empty_like(U)
     dto = ctypes.c_double(0.0)
-    bad = _load().oracle_rk3_step(ctypes.byref(_grid(table, U.shape[0], gamma, eta1)), _ptr(U),
-                                  _ptr(W1), _ptr(W2), float(cfl), float(dt), ctypes.byref(dto))
+    bad = _load().oracle_rk3_step_reflux(ctypes.byref(_grid(table, U.shape[0], gamma, eta1)),
+                                         _ptr(U), _ptr(W1), _ptr(W2), float(cfl), float(dt),
+                                         ctypes.byref(dto), int(bool(reflux)))
     return U, dto.value, bad
+
+
+def step_record(table: Table, Uk, dt, beta=1.0, U0=None, leaves=None, out=None, face_flux=None,
+                gamma=GAMMA, eta1=ETA1):
+    """Substep that also records the fluxes through the six faces of every
+    processed leaf into face_flux[n][3][2][64][nf] (allocated if None)."""
+    Uk = _c64(Uk)
+    U0 = None if U0 is None else _c64(U0)
+    nf = Uk.shape[0]
+    if out is None:
+        out = np.full_like(Uk, np.nan)
+    if face_flux is None:
+        face_flux = np.full((table.n_leaves, 3, 2, 64, nf), np.nan)
+    sub = None if leaves is None else np.ascontiguousarray(leaves, dtype=np.int32)
+    bad = _load().oracle_step_record(ctypes.byref(_grid(table, nf, gamma, eta1)), _ptr(U0),
+                                     _ptr(Uk), _ptr(out), float(dt), float(beta), _ptr(sub),
+                                     0 if sub is None else len(sub), _ptr(face_flux))
+    return out, face_flux, bad
+
+
+def reflux(table: Table, Uout, dt, w, face_flux, leaves=None):
+    """Coarse-fine flux correction of a substep's result (in place)."""
+    sub = None if leaves is None else np.ascontiguousarray(leaves, dtype=np.int32)
+    _load().oracle_reflux(ctypes.byref(_grid(table, Uout.shape[0], GAMMA, ETA1)), _ptr(Uout),
+                          float(dt), float(w), _ptr(face_flux), _ptr(sub),
+                          0 if sub is None else len(sub))
+    return Uout
 
 
 def step_1d(Uk, dt, beta=1.0, U0=None, gamma=GAMMA, eta1=ETA1):

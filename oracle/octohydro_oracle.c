@@ -358,8 +358,18 @@ static void combine(int has_u0, double beta, double dt, double u0, double uk, do
   *out = has_u0 ? u0 + beta * (t - u0) : t;
 }
 
+/* Position of transverse cell (u, v) in a face normal to d: u, v are the
+ * two other axes in increasing order (d=0: y,z; d=1: x,z; d=2: x,y). */
+static int32_t face_index(int32_t u, int32_t v) { return u + SUB * v; }
+
 int64_t oracle_step_subset(const ogrid* g, const double* U0, const double* Uk, double* Uout,
                            double dt, double beta, const int32_t* subset, int32_t n_subset) {
+  return oracle_step_record(g, U0, Uk, Uout, dt, beta, subset, n_subset, NULL);
+}
+
+int64_t oracle_step_record(const ogrid* g, const double* U0, const double* Uk, double* Uout,
+                           double dt, double beta, const int32_t* subset, int32_t n_subset,
+                           double* face_flux) {
   const int nf = g->nf;
   const int32_t n_work = subset ? n_subset : g->n_leaves;
   int64_t bad_total = 0;
@@ -402,6 +412,18 @@ int64_t oracle_step_subset(const ogrid* g, const double* U0, const double* Uk, d
               }
               bad_total += oracle_face_flux(d, nf, UL, UR, g->gamma, g->eta1, H[k]);
             }
+            if (face_flux) {
+              /* the fluxes through the leaf's two faces normal to d */
+              int32_t l[3];
+              l[d] = 0;
+              l[(d + 1) % 3] = a;
+              l[(d + 2) % 3] = b;
+              const int32_t u = d == 0 ? l[1] : l[0], v = d == 2 ? l[1] : l[2];
+              for (int side = 0; side < 2; ++side)
+                for (int f = 0; f < nf; ++f)
+                  face_flux[((((size_t)n * 3 + d) * 2 + side) * CELLS / SUB + face_index(u, v)) * nf +
+                            f] = H[side ? GH + SUB - 1 : GH - 1][f];
+            }
             for (int32_t i = 0; i < SUB; ++i) {
               int32_t l[3];
               l[d] = i;
@@ -429,6 +451,76 @@ int64_t oracle_step_subset(const ogrid* g, const double* U0, const double* Uk, d
 int64_t oracle_step(const ogrid* g, const double* U0, const double* Uk, double* Uout, double dt,
                     double beta) {
   return oracle_step_subset(g, U0, Uk, Uout, dt, beta, NULL, 0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coarse-fine flux correction (Sec. V-B-1: compute_fluxes "corrects these   */
+/* fluxes on coarse-fine boundaries").                                       */
+/* ------------------------------------------------------------------------ */
+
+/* After a substep, each coarse cell next to a refined face neighbour gets the
+ * flux through that face replaced by the area-weighted mean of the 4 fine
+ * fluxes the refined side computed there,
+ *   H_avg = 0.25 * ((H00 + H10) + (H01 + H11))   (first index along u),
+ * applied as a correction of the stored result: with q = (H_avg - H_c)/dx,
+ * Uout -= w dt q on the coarse cell's high face, += on its low face, where
+ * H_c is the flux the coarse leaf used and w = 1 (first stage) or beta.
+ * Faces are visited in the order x, y, z and low before high.  face_flux
+ * holds the fluxes recorded by oracle_step_record for every leaf involved. */
+void oracle_reflux(const ogrid* g, double* Uout, double dt, double w, const double* face_flux,
+                   const int32_t* subset, int32_t n_subset) {
+  const int nf = g->nf;
+  const int32_t n_work = subset ? n_subset : g->n_leaves;
+  const double wdt = w * dt;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int32_t it = 0; it < n_work; ++it) {
+    const int32_t c = subset ? subset[it] : it;
+    const int32_t L = g->coord[4 * c + 0];
+    const double inv_dx = (double)(SUB * (g->base << L));
+    for (int d = 0; d < 3; ++d)
+      for (int side = 0; side < 2; ++side) {
+        int32_t r[3] = {0, 0, 0};
+        r[d] = side ? 1 : -1;
+        const int32_t slot = (r[2] + 1) * 9 + (r[1] + 1) * 3 + (r[0] + 1);
+        if (g->kind[27 * c + slot] != ORACLE_SAME_REFINED) continue;
+        const int32_t node = g->nbr[27 * c + slot];
+        for (int32_t v = 0; v < SUB; ++v)
+          for (int32_t u = 0; u < SUB; ++u) {
+            /* the coarse face cell (u, v) is covered by fine faces (2u+i, 2v+j) */
+            double Hf[2][2][ORACLE_MAX_NF];
+            for (int j = 0; j < 2; ++j)
+              for (int i = 0; i < 2; ++i) {
+                const int32_t fu = 2 * u + i, fv = 2 * v + j;
+                int32_t ch[3];
+                ch[d] = side ? 0 : 1; /* children on the near side of the node */
+                ch[d == 0 ? 1 : 0] = fu >> 3;
+                ch[d == 2 ? 1 : 2] = fv >> 3;
+                const int32_t fine = g->children[8 * node + ch[2] * 4 + ch[1] * 2 + ch[0]];
+                /* the fine leaf's face on the coarse side: its low face when the
+                 * coarse cell lies below it, else its high face */
+                const int fside = side ? 0 : 1;
+                const double* src =
+                    face_flux + ((((size_t)fine * 3 + d) * 2 + fside) * CELLS / SUB +
+                                 face_index(fu & 7, fv & 7)) * nf;
+                for (int f = 0; f < nf; ++f) Hf[i][j][f] = src[f];
+              }
+            const double* hc =
+                face_flux + ((((size_t)c * 3 + d) * 2 + side) * CELLS / SUB + face_index(u, v)) * nf;
+            int32_t l[3];
+            l[d] = side ? SUB - 1 : 0;
+            l[d == 0 ? 1 : 0] = u;
+            l[d == 2 ? 1 : 2] = v;
+            const int32_t cell = l[2] * 64 + l[1] * 8 + l[0];
+            for (int f = 0; f < nf; ++f) {
+              const double havg =
+                  0.25 * ((Hf[0][0][f] + Hf[1][0][f]) + (Hf[0][1][f] + Hf[1][1][f]));
+              const double q = (havg - hc[f]) * inv_dx;
+              double* out = &Uout[((size_t)f * g->n_leaves + c) * CELLS + cell];
+              *out = side ? *out - wdt * q : *out + wdt * q;
+            }
+          }
+      }
+  }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -485,12 +577,23 @@ void oracle_totals(const ogrid* g, const double* U, double* out) {
 
 int64_t oracle_rk3_step(const ogrid* g, double* U, double* W1, double* W2, double cfl,
                         double dt_in, double* dt_out) {
+  return oracle_rk3_step_reflux(g, U, W1, W2, cfl, dt_in, dt_out, 0);
+}
+
+int64_t oracle_rk3_step_reflux(const ogrid* g, double* U, double* W1, double* W2, double cfl,
+                               double dt_in, double* dt_out, int reflux) {
   const double dt = dt_in > 0.0 ? dt_in : oracle_cfl_dt(g, U, cfl);
   const size_t total = (size_t)g->nf * g->n_leaves * CELLS;
+  double* ff = reflux ? (double*)malloc(sizeof(double) * (size_t)g->n_leaves * 6 * 64 * g->nf)
+                      : NULL;
   int64_t bad = 0;
-  bad += oracle_step(g, NULL, U, W1, dt, 1.0);
-  bad += oracle_step(g, U, W1, W2, dt, 0.25);
-  bad += oracle_step(g, U, W2, W1, dt, 2.0 / 3.0);
+  bad += oracle_step_record(g, NULL, U, W1, dt, 1.0, NULL, 0, ff);
+  if (ff) oracle_reflux(g, W1, dt, 1.0, ff, NULL, 0);
+  bad += oracle_step_record(g, U, W1, W2, dt, 0.25, NULL, 0, ff);
+  if (ff) oracle_reflux(g, W2, dt, 0.25, ff, NULL, 0);
+  bad += oracle_step_record(g, U, W2, W1, dt, 2.0 / 3.0, NULL, 0, ff);
+  if (ff) oracle_reflux(g, W1, dt, 2.0 / 3.0, ff, NULL, 0);
+  free(ff);
   memcpy(U, W1, sizeof(double) * total);
   if (dt_out) *dt_out = dt;
   return bad;

@@ -33,6 +33,16 @@ int64_t oracle_step(const ogrid* g, const double* U0, const double* Uk, double* 
  * other leaves is left untouched). */
 int64_t oracle_step_subset(const ogrid* g, const double* U0, const double* Uk, double* Uout,
                            double dt, double beta, const int32_t* subset, int32_t n_subset);
+/* Same, also recording into face_flux (if not NULL) the fluxes through the
+ * six faces of every processed leaf: [leaf][d][side][v][u][nf] with u, v the
+ * other two axes in increasing order and side 0 = low face, 1 = high face. */
+int64_t oracle_step_record(const ogrid* g, const double* U0, const double* Uk, double* Uout,
+                           double dt, double beta, const int32_t* subset, int32_t n_subset,
+                           double* face_flux);
+void oracle_reflux(const ogrid* g, double* Uout, double dt, double w, const double* face_flux,
+                   const int32_t* subset, int32_t n_subset);
+int64_t oracle_rk3_step_reflux(const ogrid* g, double* U, double* W1, double* W2, double cfl,
+                               double dt_in, double* dt_out, int reflux);
 double oracle_cfl_dt(const ogrid* g, const double* U, double cfl);
 void oracle_totals(const ogrid* g, const double* U, double* out);
 int64_t oracle_rk3_step(const ogrid* g, double* U, double* W1, double* W2, double cfl,

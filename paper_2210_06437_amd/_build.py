@@ -26,8 +26,8 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    tmp = LIB + ".tmp"
+def build(verbose: bool = False, extra=(), out: str = LIB) -> str:
+    tmp = out + ".tmp"
     cmd = [HIPCC, *FLAGS, *extra, "-o", tmp, *SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -39,8 +39,8 @@ def build(verbose: bool = False, extra=()) -> str:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{err}")
     if verbose and err.strip():
         print(err, file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

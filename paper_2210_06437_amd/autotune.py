@@ -1,0 +1,90 @@
+"""Autotuner for the launch options of the fused substep kernel.
+
+For each (dtype, n_fields) it times every choice of register budget (1 or 2
+wavefronts per SIMD) and XCD remap (off/on) on a workload of the benchmark's
+shape, through the C-ABI, and records the fastest in ``tuning.json`` next to
+this file.  ``binding.py`` applies the recorded choices when it is imported.
+
+Run on the GPU:  python -m paper_2210_06437_amd.autotune [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+from . import binding as hb
+from . import inputs
+
+TUNING_PATH = hb.TUNING_PATH
+
+
+def _time_step(torch, grid, U, A, B, dt, reps):
+    hb.hydro_step(grid, U, A, B, dt, 0.25)  # warm-up (also loads the kernel)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        hb.hydro_step(grid, U, A, B, dt, 0.25)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def tune_workload(torch, w, dtype, reps=3):
+    grid = hb.Grid(w.leaf_coord, w.base, w.nf, dtype)
+    tdt = torch.float64 if dtype == hb.HYDRO_F64 else torch.float32
+    U = torch.from_numpy(w.U).to("cuda").to(tdt).contiguous()
+    A, B = grid.empty_state(), grid.empty_state()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hb.hydro_cfl_dt(grid, U, 0.4, dt)
+    hb.hydro_step(grid, None, U, A, dt, 1.0)
+    results = []
+    for waves in (1, 2):
+        for remap in (0, 1):
+            hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_SIMD, waves)
+            hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_XCD_REMAP, remap)
+            ms = _time_step(torch, grid, U, A, B, dt, reps)
+            results.append({"waves_per_simd": waves, "xcd_remap": remap, "ms": ms})
+            print(f"[autotune] dtype={dtype} nf={w.nf} waves={waves} remap={remap}: {ms:.3f} ms",
+                  file=sys.stderr, flush=True)
+    best = min(results, key=lambda r: r["ms"])
+    hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_SIMD, best["waves_per_simd"])
+    hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_XCD_REMAP, best["xcd_remap"])
+    del U, A, B
+    torch.cuda.empty_cache()
+    return {"dtype": dtype, "n_fields": w.nf, "waves_per_simd": best["waves_per_simd"],
+            "xcd_remap": best["xcd_remap"], "ms": best["ms"], "workload": w.name,
+            "leaves": w.n_leaves, "all": results}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true", help="smaller workloads")
+    ap.add_argument("--out", default=TUNING_PATH)
+    args = ap.parse_args()
+    import torch
+    assert torch.cuda.is_available(), "the autotuner needs a GPU"
+    t0 = time.time()
+    w11 = inputs.turbulence(base=16 if args.quick else 32, n_refine=585 if args.quick else 4681)
+    w6 = inputs.sod(base=16 if args.quick else 32)
+    entries = []
+    for w in (w11, w6):
+        for dtype in (hb.HYDRO_F64, hb.HYDRO_F32):
+            entries.append(tune_workload(torch, w, dtype))
+    out = {"arch": torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
+           "seconds": time.time() - t0, "entries": entries}
+    with open(args.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({"wrote": args.out, "choices": [
+        {k: e[k] for k in ("dtype", "n_fields", "waves_per_simd", "xcd_remap", "ms")}
+        for e in entries]}))
+
+
+if __name__ == "__main__":
+    main()

@@ -18,7 +18,9 @@ import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "liboctohydro.so")
+# OCTOHYDRO_LIB may name another build of the same library (e.g. a tuning
+# variant); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("OCTOHYDRO_LIB") or os.path.join(_PKG, "liboctohydro.so")
 
 HYDRO_OK, HYDRO_E_ARG, HYDRO_E_TABLE, HYDRO_E_UNPHYSICAL, HYDRO_E_HIP, HYDRO_E_UNSUPPORTED = (
     0, -1, -2, -3, -4, -5)
@@ -31,8 +33,9 @@ EXPORTS = [
     "hydro_build_table", "hydro_fill_ghosts", "hydro_step", "hydro_step_per_leaf",
     "hydro_cfl_dt", "hydro_totals", "hydro_rk3_step", "hydro_rk3_graph_create",
     "hydro_graph_launch", "hydro_graph_destroy", "hydro_check_status", "hydro_last_error",
-    "hydro_version",
+    "hydro_version", "hydro_set_option", "hydro_get_option",
 ]
+HYDRO_OPT_WAVES_PER_SIMD, HYDRO_OPT_XCD_REMAP = 1, 2
 
 
 class HydroError(RuntimeError):
@@ -81,6 +84,8 @@ def _load():
         "hydro_check_status": ([G, vp], ctypes.c_int),
         "hydro_last_error": ([], ctypes.c_char_p),
         "hydro_version": ([], ctypes.c_int),
+        "hydro_set_option": ([i32, i32, i32, i32], ctypes.c_int),
+        "hydro_get_option": ([i32, i32, i32, ctypes.POINTER(i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -90,6 +95,27 @@ def _load():
 
 
 _lib = _load()
+
+# Launch options chosen by the autotuner (autotune.py), applied at import.
+TUNING_PATH = os.path.join(_PKG, "tuning.json")
+
+
+def apply_tuning(path: str = TUNING_PATH) -> int:
+    """Apply recorded autotuner choices; returns how many entries were set."""
+    import json
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        data = json.load(f)
+    n = 0
+    for e in data.get("entries", []):
+        _lib.hydro_set_option(int(e["dtype"]), int(e["n_fields"]), 1, int(e["waves_per_simd"]))
+        _lib.hydro_set_option(int(e["dtype"]), int(e["n_fields"]), 2, int(e["xcd_remap"]))
+        n += 1
+    return n
+
+
+apply_tuning()
 
 
 def _check(rc: int):
@@ -115,6 +141,16 @@ def hydro_version() -> int:
 
 def hydro_last_error() -> str:
     return _lib.hydro_last_error().decode()
+
+
+def hydro_set_option(dtype: int, n_fields: int, option: int, value: int):
+    _check(_lib.hydro_set_option(int(dtype), int(n_fields), int(option), int(value)))
+
+
+def hydro_get_option(dtype: int, n_fields: int, option: int) -> int:
+    v = ctypes.c_int32(0)
+    _check(_lib.hydro_get_option(int(dtype), int(n_fields), int(option), ctypes.byref(v)))
+    return v.value
 
 
 def hydro_build_table(leaf_coord: np.ndarray, base: int):

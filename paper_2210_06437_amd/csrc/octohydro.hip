@@ -173,8 +173,9 @@ __device__ __forceinline__ void monotonise(T c, T& l, T& r) {
   r = nr;
 }
 
-// Feed q[k]; when k >= 5, returns the face states of the face between tile
-// cells k-3 and k-2 in (UL, UR).  k is a compile-time constant after unroll.
+// Feed the k-th value of a pencil stream; when k >= 5, returns the face
+// states of the face between stream cells k-3 and k-2 in (UL, UR).  k is a
+// compile-time constant after unrolling.
 template <typename T>
 __device__ __forceinline__ void ppm_push(Ppm<T>& s, T qn, int k, T& UL, T& UR) {
   T dm_new = T(0), qf_new = T(0), Lc = T(0), Rc = T(0);
@@ -207,6 +208,12 @@ struct Phys {
   T gamma, gm1, eta1;
 };
 
+// Internal energy density from the entropy tracer, tau^gamma (dual-energy
+// switch).  Kept out of line: the branch is rare and the inlined pow would
+// hold registers in the hot loop.
+__device__ __noinline__ double tau_energy(double tau, double gamma) { return pow(tau, gamma); }
+__device__ __noinline__ float tau_energy(float tau, float gamma) { return powf(tau, gamma); }
+
 // rinv = 1/rho, p, c for conserved state (rho, sx, sy, sz, E, tau).
 template <typename T>
 __device__ __forceinline__ bool eos(const Phys<T>& ph, T rho, T sx, T sy, T sz, T E, T tau,
@@ -214,7 +221,7 @@ __device__ __forceinline__ bool eos(const Phys<T>& ph, T rho, T sx, T sy, T sz, 
   rinv = T(1) / rho;
   const T ss = (sx * sx + sy * sy) + sz * sz;
   T ei = E - T(0.5) * ss * rinv;
-  if (ei < ph.eta1 * E) ei = pow(tau, ph.gamma);
+  if (ei < ph.eta1 * E) ei = tau_energy(tau, ph.gamma);
   p = ph.gm1 * ei;
   c = sqrt(ph.gamma * p * rinv);
   return !(rho > T(0)) || !(p > T(0));
@@ -235,192 +242,350 @@ struct StepArgs {
   int32_t remap;      // 1: spread contiguous leaf ranges over the 8 XCDs
 };
 
-// Strides of a cell (pos along axis D, a, b transverse) inside a leaf.
-template <int D>
-struct Axes;
-template <>
-struct Axes<0> {
-  static constexpr int SD = 1, SA = 8, SB = 64, A = 1, B = 2;
-};
-template <>
-struct Axes<1> {
-  static constexpr int SD = 8, SA = 1, SB = 64, A = 0, B = 2;
-};
-template <>
-struct Axes<2> {
-  static constexpr int SD = 64, SA = 1, SB = 8, A = 0, B = 1;
-};
-
-template <int D>
-__device__ __forceinline__ int acc_index(int i, int a, int b) {
-  int c[3];
-  c[D] = i;
-  c[Axes<D>::A] = a;
-  c[Axes<D>::B] = b;
-  return c[2] * ACC_PLANE + c[1] * ACC_PITCH + c[0];
-}
-
+// Per-leaf constants.  Neighbour kinds and ids of the six face neighbours are
+// handed to the phases as plain values (the phase picks its axis once), so
+// no per-lane choice is ever made by indexing memory.
 struct LeafInfo {
-  int leaf;
-  int ic[3];
-  int blocks;
-  int kind_lo[3], id_lo[3], kind_hi[3], id_hi[3];
+  int leaf, blocks;
+  int ix, iy, iz;
 };
 
-// Value at tile position k (0..13) of the pencil along D through (a, b).
-template <typename T, int D>
-__device__ __forceinline__ T pencil_value(const GridArgs& g, const T* __restrict__ Uf,
-                                          const LeafInfo& li, int k, int a, int b) {
-  using X = Axes<D>;
-  if (k >= GH && k < GH + SUB)
-    return Uf[(size_t)li.leaf * CELLS + (k - GH) * X::SD + a * X::SA + b * X::SB];
-  const bool hi = k >= GH + SUB;
-  int r[3] = {0, 0, 0}, l[3];
-  r[D] = hi ? 1 : -1;
-  l[D] = hi ? k - GH - SUB : k - GH + SUB;
-  l[X::A] = a;
-  l[X::B] = b;
-  return neighbour_value<T>(g, Uf, li.leaf, li.ic, li.blocks, hi ? li.kind_hi[D] : li.kind_lo[D],
-                            hi ? li.id_hi[D] : li.id_lo[D], r, l);
+// Face neighbour (kind, id) of a pencil axis, low and high side.
+struct FaceNbr {
+  int klo, ilo, khi, ihi;
+};
+
+// A lane's pencil along axis d through transverse cell (a, b): where each of
+// its 14 stream values comes from.  Interior values sit at off + (k-3) sd in
+// the leaf; each ghost value k in {0,1,2,11,12,13} comes from the element
+// offset gofs[] of the field array -- a same-level cell, the covering coarse
+// cell (injection), or, on a refined side, the first of the 8 fine cells it
+// averages, which lie at +{0,1,8,9,64,65,72,73}.  The sources are the same
+// for every field, so they are worked out once per pencil.
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+
+struct Pencil {
+  uint32_t off, sd;
+  u32x8 gofs;  // a vector value: selecting an entry never touches memory
+  bool ref_lo, ref_hi;
+};
+
+__device__ __forceinline__ uint32_t ghost_offset(const GridArgs& g, const LeafInfo& li, int kind,
+                                                 int id, int side, int d, int lx, int ly,
+                                                 int lz) {
+  if (kind == HYDRO_SAME_LEAF) return id * CELLS + lz * 64 + ly * 8 + lx;
+  if (kind == HYDRO_COARSER_LEAF) {
+    // the neighbour block along d, wrapped; transverse blocks are the leaf's
+    const int nb = wrap((d == 0 ? li.ix : (d == 1 ? li.iy : li.iz)) + side, li.blocks);
+    const int bx = d == 0 ? nb : li.ix, by = d == 1 ? nb : li.iy, bz = d == 2 ? nb : li.iz;
+    return id * CELLS + (4 * (bz & 1) + (lz >> 1)) * 64 + (4 * (by & 1) + (ly >> 1)) * 8 +
+           (4 * (bx & 1) + (lx >> 1));
+  }
+  const int child = g.children[8 * id + (lz >> 2) * 4 + (ly >> 2) * 2 + (lx >> 2)];
+  return child * CELLS + ((2 * lz) & 7) * 64 + ((2 * ly) & 7) * 8 + ((2 * lx) & 7);
 }
 
-// One axis of the substep for one leaf; lane = pencil (a, b).
-template <typename T, int NF, int D>
-__device__ __forceinline__ void axis_pass(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
-                                          double* __restrict__ acc, double dt, double inv_dx,
-                                          int lane, bool& bad) {
+__device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo& li, int d, int a,
+                                              int b, const FaceNbr& fn) {
+  Pencil p;
+  // d = 0: (x, a=y, b=z); d = 1: (a=x, y, b=z); d = 2: (a=x, b=y, z)
+  p.off = li.leaf * CELLS + (d == 0 ? b * 64 + a * 8 : (d == 1 ? b * 64 + a : b * 8 + a));
+  p.sd = d == 0 ? 1 : (d == 1 ? 8 : 64);
+  const int klo = fn.klo, ilo = fn.ilo, khi = fn.khi, ihi = fn.ihi;
+  p.ref_lo = klo == HYDRO_SAME_REFINED;
+  p.ref_hi = khi == HYDRO_SAME_REFINED;
+#pragma unroll
+  for (int j = 0; j < 2 * GH; ++j) {
+    const bool hi = j >= GH;
+    const int l = hi ? j - GH : j + SUB - GH;  // cell along d inside the neighbour block
+    const int lx = d == 0 ? l : a;
+    const int ly = d == 0 ? a : (d == 1 ? l : b);
+    const int lz = d == 2 ? l : b;
+    p.gofs[j] = ghost_offset(g, li, hi ? khi : klo, hi ? ihi : ilo, hi ? 1 : -1, d, lx, ly, lz);
+  }
+  return p;
+}
+
+// Value at stream position k (0..13) of a lane's pencil in field array Uf.
+#ifndef OCTOHYDRO_GOFS_CHAIN
+#define OCTOHYDRO_GOFS_CHAIN 0
+#endif
+#ifndef OCTOHYDRO_FENCE_RESTRICT
+#define OCTOHYDRO_FENCE_RESTRICT 0
+#endif
+#if OCTOHYDRO_FENCE_RESTRICT
+#define OCTOHYDRO_RFENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define OCTOHYDRO_RFENCE() ((void)0)
+#endif
+
+// Element `off` of a field array whose base address is the same for every
+// lane.  The byte offset is formed in 32 bits (one field array is far below
+// 4 GiB), so the load takes the uniform base in scalar registers and one
+// 32-bit lane offset that all fields share.
+template <typename T>
+__device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                     (uint32_t)(off * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st(T* __restrict__ base, uint32_t off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T))) = v;
+}
+
+// Uf is the field's base address (the same for every lane); all per-lane
+// addressing is a 32-bit element offset from it.
+template <typename T>
+__device__ __forceinline__ T pencil_value(const T* __restrict__ Uf, const Pencil& p, int k) {
+  if (k >= GH && k < GH + SUB) return ld(Uf, p.off + (uint32_t)(k - GH) * p.sd);
+#if OCTOHYDRO_GOFS_CHAIN
+  const uint32_t go = k == 0 ? p.gofs[0] : k == 1 ? p.gofs[1] : k == 2 ? p.gofs[2]
+                    : k == 11 ? p.gofs[3] : k == 12 ? p.gofs[4] : p.gofs[5];
+#else
+  const uint32_t go = p.gofs[k < GH ? k : k - SUB];
+#endif
+  T v;
+  if (k < GH ? p.ref_lo : p.ref_hi) {
+    OCTOHYDRO_RFENCE();
+    v = T(0.125) * (((ld(Uf, go) + ld(Uf, go + 1u)) + (ld(Uf, go + 8u) + ld(Uf, go + 9u))) +
+                    ((ld(Uf, go + 64u) + ld(Uf, go + 65u)) + (ld(Uf, go + 72u) + ld(Uf, go + 73u))));
+    OCTOHYDRO_RFENCE();
+  } else {
+    v = ld(Uf, go);
+  }
+  return v;
+}
+
+// Kurganov-Tadmor fluxes of the core fields at one face normal to axis d;
+// also returns the face's normal velocities and half the signal speed for
+// the passive species.
+template <typename T>
+__device__ __forceinline__ void core_flux(const Phys<T>& ph, int d, const T (&UL)[NF_CORE],
+                                          const T (&UR)[NF_CORE], T (&H)[NF_CORE], T& vL, T& vR,
+                                          T& ha, bool& bad) {
+  T riL, pL, cL, riR, pR, cR;
+  bad |= eos(ph, UL[0], UL[1], UL[2], UL[3], UL[4], UL[5], riL, pL, cL);
+  bad |= eos(ph, UR[0], UR[1], UR[2], UR[3], UR[4], UR[5], riR, pR, cR);
+  const T snL = d == 0 ? UL[1] : (d == 1 ? UL[2] : UL[3]);
+  const T snR = d == 0 ? UR[1] : (d == 1 ? UR[2] : UR[3]);
+  vL = snL * riL;
+  vR = snR * riR;
+  ha = T(0.5) * fmax(fabs(vL) + cL, fabs(vR) + cR);
+  T FL[NF_CORE], FR[NF_CORE];
+  FL[0] = snL;
+  FR[0] = snR;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const T fl = UL[1 + m] * vL;
+    const T fr = UR[1 + m] * vR;
+    FL[1 + m] = m == d ? fl + pL : fl;
+    FR[1 + m] = m == d ? fr + pR : fr;
+  }
+  FL[4] = (UL[4] + pL) * vL;
+  FR[4] = (UR[4] + pR) * vR;
+  FL[5] = UL[5] * vL;
+  FR[5] = UR[5] * vR;
+#pragma unroll
+  for (int f = 0; f < NF_CORE; ++f) H[f] = T(0.5) * (FL[f] + FR[f]) - ha * (UR[f] - UL[f]);
+}
+
+// Stage combination of one cell: t = Uk + dt L with L = -sum * inv_dx, then
+// t (first stage) or U0 + beta (t - U0).
+template <typename T>
+__device__ __forceinline__ void finish_cell(const StepArgs& s, size_t fbase, uint32_t cell, T uk,
+                                            double sum, double dt, double inv_dx) {
+  const double lrate = -sum * inv_dx;
+  const double t = (double)uk + dt * lrate;
+  double out;
+  if (s.U0) {
+    const double u0 = (double)ld(static_cast<const T*>(s.U0) + fbase, cell);
+    out = u0 + s.beta * (t - u0);
+  } else {
+    out = t;
+  }
+  st(static_cast<T*>(s.Uout) + fbase, cell, (T)out);
+}
+
+// Scheduling fence between the per-field PPM evaluations: without it the
+// scheduler interleaves all fields for ILP and runs out of registers.
+#ifndef OCTOHYDRO_FENCE_FIELDS
+#define OCTOHYDRO_FENCE_FIELDS 0
+#endif
+#if OCTOHYDRO_FENCE_FIELDS
+#define OCTOHYDRO_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define OCTOHYDRO_FENCE() ((void)0)
+#endif
+
+// LDS accumulator of half a leaf (4 z-planes): field stride ACC_HALF.
+constexpr int ACC_HALF = 4 * ACC_PLANE;
+
+// First five stream steps of all NF fields of a pencil (stream positions
+// k0..k0+4): they build the PPM recurrences up to the first complete cell;
+// no face is complete yet.  Unrolled, so each step does only the work its
+// stencil allows.
+template <typename T, int NF>
+__device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], const T* __restrict__ Uk,
+                                                size_t fs, const Pencil& p, int k0) {
+  T q[5][NF];
+#pragma unroll
+  for (int j = 0; j < 5; ++j)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) q[j][f] = pencil_value<T>(Uk + f * fs, p, k0 + j);
+#pragma unroll
+  for (int j = 0; j < 5; ++j)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      T ul, ur;
+      ppm_push(st[f], q[j][f], j, ul, ur);
+    }
+}
+
+// A steady stream step: feed the next value of every field and evaluate the
+// face between stream cells k-3 and k-2 (fluxes in H).
+template <typename T, int NF>
+__device__ __forceinline__ void stream_step(const Phys<T>& ph, int d, Ppm<T> (&st)[NF],
+                                            const T (&qn)[NF], T (&H)[NF], bool& bad) {
+  T UL[NF], UR[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    ppm_push(st[f], qn[f], 5, UL[f], UR[f]);
+    OCTOHYDRO_FENCE();
+  }
+  T core_L[NF_CORE], core_R[NF_CORE], Hc[NF_CORE], vL, vR, ha;
+#pragma unroll
+  for (int f = 0; f < NF_CORE; ++f) {
+    core_L[f] = UL[f];
+    core_R[f] = UR[f];
+  }
+  core_flux(ph, d, core_L, core_R, Hc, vL, vR, ha, bad);
+#pragma unroll
+  for (int f = 0; f < NF_CORE; ++f) H[f] = Hc[f];
+#pragma unroll
+  for (int f = NF_CORE; f < NF; ++f)
+    H[f] = T(0.5) * (UL[f] * vL + UR[f] * vR) - ha * (UR[f] - UL[f]);
+}
+
+// Phase XY of half h: lanes 0-31 stream x-pencils, lanes 32-63 y-pencils of
+// the planes z in [4h, 4h+4).  Each cell receives dHx from one lane and dHy
+// from another; the lane that reaches the cell first (the x-lane on ties)
+// stores, the other adds after a wave-level ordering point.  A sum of two
+// binary64 values does not depend on their order, so the accumulator holds
+// exactly dHx + dHy.
+template <typename T, int NF>
+__device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
+                                         const FaceNbr& fn, double* __restrict__ acc, int h,
+                                         int lane, bool& bad) {
   const GridArgs& g = s.g;
-  const int a = lane & 7, b = lane >> 3;
   const size_t fs = (size_t)g.n_leaves * CELLS;
   const T* __restrict__ Uk = static_cast<const T*>(s.Uk);
+  const int d = lane >> 5;
+  const int a = lane & 7;
+  const int zz = (lane >> 3) & 3;
+  const Pencil p = make_pencil(g, li, d, a, 4 * h + zz, fn);
+  const int acc_off = d == 0 ? zz * ACC_PLANE + a * ACC_PITCH : zz * ACC_PLANE + a;
+  const int acc_step = d == 0 ? 1 : ACC_PITCH;
 
-  // Face speeds from the core pass, reused by the passive species.
-  T vLf[SUB + 1], vRf[SUB + 1], haf[SUB + 1];
-
-  // ---- core fields: rho, s, E, tau ----
-  {
-    Ppm<T> st[NF_CORE];
-    double Hprev[NF_CORE];
-    T UL[NF_CORE], UR[NF_CORE];
+  Ppm<T> st[NF];
+  double Hprev[NF];
 #pragma unroll
-    for (int f = 0; f < NF_CORE; ++f) {
-      st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
-      Hprev[f] = 0.0;
-      UL[f] = UR[f] = T(0);
-    }
-#pragma unroll
-    for (int k = 0; k < TW; ++k) {
-#pragma unroll
-      for (int f = 0; f < NF_CORE; ++f) {
-        const T q = pencil_value<T, D>(g, Uk + f * fs, li, k, a, b);
-        ppm_push(st[f], q, k, UL[f], UR[f]);
-      }
-      if (k >= 5) {
-        const int face = k - 5;  // low face of interior cell `face`
-        T riL, pL, cL, riR, pR, cR;
-        bad |= eos(ph, UL[0], UL[1], UL[2], UL[3], UL[4], UL[5], riL, pL, cL);
-        bad |= eos(ph, UR[0], UR[1], UR[2], UR[3], UR[4], UR[5], riR, pR, cR);
-        const T vL = UL[1 + D] * riL;
-        const T vR = UR[1 + D] * riR;
-        const T ha = T(0.5) * fmax(fabs(vL) + cL, fabs(vR) + cR);
-        vLf[face] = vL;
-        vRf[face] = vR;
-        haf[face] = ha;
-        T FL[NF_CORE], FR[NF_CORE];
-        FL[0] = UL[1 + D];
-        FR[0] = UR[1 + D];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          FL[1 + m] = UL[1 + m] * vL;
-          FR[1 + m] = UR[1 + m] * vR;
-        }
-        FL[1 + D] = FL[1 + D] + pL;
-        FR[1 + D] = FR[1 + D] + pR;
-        FL[4] = (UL[4] + pL) * vL;
-        FR[4] = (UR[4] + pR) * vR;
-        FL[5] = UL[5] * vL;
-        FR[5] = UR[5] * vR;
-#pragma unroll
-        for (int f = 0; f < NF_CORE; ++f) {
-          const T Ht = T(0.5) * (FL[f] + FR[f]) - ha * (UR[f] - UL[f]);
-          const double H = (double)Ht;
-          if (face >= 1) {
-            const int i = face - 1;
-            const double dH = H - Hprev[f];
-            const int ai = f * ACC_FIELD + acc_index<D>(i, a, b);
-            if constexpr (D == 0) {
-              acc[ai] = dH;
-            } else if constexpr (D == 1) {
-              acc[ai] = acc[ai] + dH;
-            } else {
-              const double sum = acc[ai] + dH;
-              const double lrate = -sum * inv_dx;
-              const int cell = (i)*64 + b * 8 + a;
-              const size_t at = (size_t)f * fs + (size_t)li.leaf * CELLS + cell;
-              const double t = (double)st[f].qy + dt * lrate;
-              double out;
-              if (s.U0) {
-                const double u0 = (double)static_cast<const T*>(s.U0)[at];
-                out = u0 + s.beta * (t - u0);
-              } else {
-                out = t;
-              }
-              static_cast<T*>(s.Uout)[at] = (T)out;
-            }
-          }
-          Hprev[f] = H;
-        }
-      }
-    }
+  for (int f = 0; f < NF; ++f) {
+    st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    Hprev[f] = 0.0;
   }
-
-  // ---- passive species: flux rho_k v_n with the same dissipation ----
-#pragma unroll 1
-  for (int f = NF_CORE; f < NF; ++f) {
-    Ppm<T> st{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
-    double Hprev = 0.0;
-    T ULs = T(0), URs = T(0);
+  stream_prologue<T, NF>(st, Uk, fs, p, 0);
+  T qnext[NF];
 #pragma unroll
-    for (int k = 0; k < TW; ++k) {
-      const T q = pencil_value<T, D>(g, Uk + f * fs, li, k, a, b);
-      ppm_push(st, q, k, ULs, URs);
-      if (k >= 5) {
-        const int face = k - 5;
-        const T Ht = T(0.5) * (ULs * vLf[face] + URs * vRf[face]) - haf[face] * (URs - ULs);
-        const double H = (double)Ht;
-        if (face >= 1) {
-          const int i = face - 1;
-          const double dH = H - Hprev;
-          const int ai = f * ACC_FIELD + acc_index<D>(i, a, b);
-          if constexpr (D == 0) {
-            acc[ai] = dH;
-          } else if constexpr (D == 1) {
-            acc[ai] = acc[ai] + dH;
-          } else {
-            const double sum = acc[ai] + dH;
-            const double lrate = -sum * inv_dx;
-            const int cell = i * 64 + b * 8 + a;
-            const size_t at = (size_t)f * fs + (size_t)li.leaf * CELLS + cell;
-            const double t = (double)st.qy + dt * lrate;
-            double out;
-            if (s.U0) {
-              const double u0 = (double)static_cast<const T*>(s.U0)[at];
-              out = u0 + s.beta * (t - u0);
-            } else {
-              out = t;
-            }
-            static_cast<T*>(s.Uout)[at] = (T)out;
-          }
-        }
-        Hprev = H;
+  for (int f = 0; f < NF; ++f) qnext[f] = pencil_value<T>(Uk + f * fs, p, 5);
+#pragma unroll 1
+  for (int k = 5; k < TW; ++k) {
+    T qn[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) qn[f] = qnext[f];
+    if (k + 1 < TW) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) qnext[f] = pencil_value<T>(Uk + f * fs, p, k + 1);
+    }
+    T H[NF];
+    stream_step<T, NF>(ph, d, st, qn, H, bad);
+    if (k >= 6) {
+      const int i = k - 6;  // interior cell along d: H now is its high face
+      const bool first = d == 0 ? i <= a : i < a;
+      const int ai = acc_off + i * acc_step;
+      double dH[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) dH[f] = (double)H[f] - Hprev[f];
+      if (first) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f * ACC_HALF + ai] = dH[f];
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (!first) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f * ACC_HALF + ai] = acc[f * ACC_HALF + ai] + dH[f];
       }
     }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) Hprev[f] = (double)H[f];
   }
 }
 
+// Phase Z of half h: lane (x, y) streams its z-pencil over stream positions
+// [4h, 4h+10), which yields the z-faces of cells z in [4h, 4h+4), adds dHz
+// to the accumulator and finishes those cells.
 template <typename T, int NF>
-__global__ void __launch_bounds__(64) k_step(StepArgs s) {
-  __shared__ double acc[NF * ACC_FIELD];
+__device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
+                                        const FaceNbr& fn, const double* __restrict__ acc, int h,
+                                        int lane, double dt, double inv_dx, bool& bad) {
+  const GridArgs& g = s.g;
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const T* __restrict__ Uk = static_cast<const T*>(s.Uk);
+  const int x = lane & 7, y = lane >> 3;
+  const Pencil p = make_pencil(g, li, 2, x, y, fn);
+  const int k0 = 4 * h;
+  const uint32_t leaf_at = (uint32_t)li.leaf * CELLS + y * 8 + x;
+
+  Ppm<T> st[NF];
+  double Hprev[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    Hprev[f] = 0.0;
+  }
+  stream_prologue<T, NF>(st, Uk, fs, p, k0);
+  T qnext[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) qnext[f] = pencil_value<T>(Uk + f * fs, p, k0 + 5);
+#pragma unroll 1
+  for (int kk = 5; kk < 10; ++kk) {
+    const int k = k0 + kk;
+    T qn[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) qn[f] = qnext[f];
+    if (kk + 1 < 10) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) qnext[f] = pencil_value<T>(Uk + f * fs, p, k + 1);
+    }
+    T H[NF];
+    stream_step<T, NF>(ph, 2, st, qn, H, bad);
+    if (kk >= 6) {
+      const int i = k - 6;  // interior cell along z
+      const int ai = (i - k0) * ACC_PLANE + y * ACC_PITCH + x;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double sum = acc[f * ACC_HALF + ai] + ((double)H[f] - Hprev[f]);
+        finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, st[f].qy, sum, dt, inv_dx);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) Hprev[f] = (double)H[f];
+  }
+}
+
+// W = register budget: W waves per SIMD (1: up to 512 VGPRs, 2: up to 256).
+template <typename T, int NF, int W>
+__global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
+  __shared__ double acc[NF * ACC_HALF];
   const GridArgs& g = s.g;
   int bid = blockIdx.x;
   if (s.remap) {
@@ -437,19 +602,23 @@ __global__ void __launch_bounds__(64) k_step(StepArgs s) {
   LeafInfo li;
   li.leaf = leaf;
   const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
-  li.ic[0] = c4.y;
-  li.ic[1] = c4.z;
-  li.ic[2] = c4.w;
+  li.ix = c4.y;
+  li.iy = c4.z;
+  li.iz = c4.w;
   li.blocks = g.base << c4.x;
   // face-neighbour slots: -x 12, +x 14, -y 10, +y 16, -z 4, +z 22
-  const int slo[3] = {12, 10, 4}, shi[3] = {14, 16, 22};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    li.kind_lo[d] = g.kind[27 * leaf + slo[d]];
-    li.id_lo[d] = g.nbr[27 * leaf + slo[d]];
-    li.kind_hi[d] = g.kind[27 * leaf + shi[d]];
-    li.id_hi[d] = g.nbr[27 * leaf + shi[d]];
-  }
+  const uint8_t* kd = g.kind + 27 * leaf;
+  const int32_t* nb = g.nbr + 27 * leaf;
+  const bool xlane = lane < 32;  // phase XY: lanes 0-31 x-pencils, 32-63 y-pencils
+  FaceNbr fxy, fz;
+  fxy.klo = xlane ? (int)kd[12] : (int)kd[10];
+  fxy.ilo = xlane ? nb[12] : nb[10];
+  fxy.khi = xlane ? (int)kd[14] : (int)kd[16];
+  fxy.ihi = xlane ? nb[14] : nb[16];
+  fz.klo = kd[4];
+  fz.ilo = nb[4];
+  fz.khi = kd[22];
+  fz.ihi = nb[22];
   const double dt = *s.dt;
   const double inv_dx = (double)(SUB * li.blocks);
   Phys<T> ph;
@@ -458,11 +627,13 @@ __global__ void __launch_bounds__(64) k_step(StepArgs s) {
   ph.eta1 = (T)g.eta1;
 
   bool bad = false;
-  axis_pass<T, NF, 0>(s, ph, li, acc, dt, inv_dx, lane, bad);
-  __syncthreads();
-  axis_pass<T, NF, 1>(s, ph, li, acc, dt, inv_dx, lane, bad);
-  __syncthreads();
-  axis_pass<T, NF, 2>(s, ph, li, acc, dt, inv_dx, lane, bad);
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    phase_xy<T, NF>(s, ph, li, fxy, acc, h, lane, bad);
+    __builtin_amdgcn_wave_barrier();
+    phase_z<T, NF>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad);
+    __builtin_amdgcn_wave_barrier();
+  }
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
 }
 
@@ -661,28 +832,52 @@ static int grid_blocks(int64_t work, int threads, int cap) {
   return (int)(b < 1 ? 1 : b);
 }
 
+// Launch options per (dtype, n_fields), set by hydro_set_option (the
+// autotuner's choices) and read at launch time.
+struct Options {
+  int waves_per_simd = 1;
+  int xcd_remap = 1;
+};
+static Options g_opts[2][17];
+static std::mutex g_opts_mu;
+
+static Options get_options(int dtype, int nf) {
+  std::lock_guard<std::mutex> lk(g_opts_mu);
+  return g_opts[dtype][nf];
+}
+
 template <typename T, int NF>
-static hipError_t launch_step_nf(const StepArgs& a, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((k_step<T, NF>), dim3(blocks), dim3(64), 0, st, a);
+static hipError_t launch_step_nf(const StepArgs& a, int blocks, int waves, hipStream_t st) {
+  if (waves == 2)
+    hipLaunchKernelGGL((k_step<T, NF, 2>), dim3(blocks), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_step<T, NF, 1>), dim3(blocks), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_step_t(const StepArgs& a, int blocks, hipStream_t st) {
+static hipError_t launch_step_t(const StepArgs& a, int blocks, int waves, hipStream_t st) {
   switch (a.g.nf) {
-    case 6: return launch_step_nf<T, 6>(a, blocks, st);
-    case 7: return launch_step_nf<T, 7>(a, blocks, st);
-    case 8: return launch_step_nf<T, 8>(a, blocks, st);
-    case 9: return launch_step_nf<T, 9>(a, blocks, st);
-    case 10: return launch_step_nf<T, 10>(a, blocks, st);
-    case 11: return launch_step_nf<T, 11>(a, blocks, st);
+    case 6: return launch_step_nf<T, 6>(a, blocks, waves, st);
+    case 7: return launch_step_nf<T, 7>(a, blocks, waves, st);
+    case 8: return launch_step_nf<T, 8>(a, blocks, waves, st);
+    case 9: return launch_step_nf<T, 9>(a, blocks, waves, st);
+    case 10: return launch_step_nf<T, 10>(a, blocks, waves, st);
+    case 11: return launch_step_nf<T, 11>(a, blocks, waves, st);
+    case 12: return launch_step_nf<T, 12>(a, blocks, waves, st);
+    case 13: return launch_step_nf<T, 13>(a, blocks, waves, st);
+    case 14: return launch_step_nf<T, 14>(a, blocks, waves, st);
+    case 15: return launch_step_nf<T, 15>(a, blocks, waves, st);
+    case 16: return launch_step_nf<T, 16>(a, blocks, waves, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-static hipError_t launch_step(const StepArgs& a, int dtype, int blocks, hipStream_t st) {
-  return dtype == HYDRO_F64 ? launch_step_t<double>(a, blocks, st)
-                            : launch_step_t<float>(a, blocks, st);
+static hipError_t launch_step(StepArgs a, int dtype, int blocks, hipStream_t st) {
+  const Options o = get_options(dtype, a.g.nf);
+  if (a.remap) a.remap = o.xcd_remap;
+  return dtype == HYDRO_F64 ? launch_step_t<double>(a, blocks, o.waves_per_simd, st)
+                            : launch_step_t<float>(a, blocks, o.waves_per_simd, st);
 }
 
 static int validate_table(const hydro_grid* gr, hipStream_t st) {
@@ -704,8 +899,6 @@ static int step_common(const hydro_grid* gr, const void* U0, const void* Uk, voi
                        StepArgs& a) {
   int rc = check_grid(gr, fn);
   if (rc) return rc;
-  if (gr->n_fields > 11)
-    return fail(HYDRO_E_UNSUPPORTED, "%s: n_fields %d > 11 not built", fn, gr->n_fields);
   if (!Uk || !Uout || !dt) return fail(HYDRO_E_ARG, "%s: Uk, Uout and dt must be set", fn);
   if (Uout == Uk || (U0 && Uout == U0))
     return fail(HYDRO_E_ARG, "%s: Uout may not alias an input", fn);
@@ -814,6 +1007,38 @@ using namespace octohydro;
 extern "C" {
 
 int hydro_version(void) { return 100; }
+
+int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t value) {
+  clear_error();
+  if ((dtype != HYDRO_F64 && dtype != HYDRO_F32) || n_fields < NF_CORE || n_fields > 16)
+    return fail(HYDRO_E_ARG, "hydro_set_option: bad dtype %d or n_fields %d", dtype, n_fields);
+  std::lock_guard<std::mutex> lk(g_opts_mu);
+  Options& o = g_opts[dtype][n_fields];
+  switch (option) {
+    case HYDRO_OPT_WAVES_PER_SIMD:
+      if (value != 1 && value != 2)
+        return fail(HYDRO_E_ARG, "hydro_set_option: waves per SIMD must be 1 or 2");
+      o.waves_per_simd = value;
+      return HYDRO_OK;
+    case HYDRO_OPT_XCD_REMAP:
+      if (value != 0 && value != 1) return fail(HYDRO_E_ARG, "hydro_set_option: remap is 0 or 1");
+      o.xcd_remap = value;
+      return HYDRO_OK;
+    default:
+      return fail(HYDRO_E_ARG, "hydro_set_option: unknown option %d", option);
+  }
+}
+
+int hydro_get_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t* value) {
+  clear_error();
+  if ((dtype != HYDRO_F64 && dtype != HYDRO_F32) || n_fields < NF_CORE || n_fields > 16 || !value)
+    return fail(HYDRO_E_ARG, "hydro_get_option: bad argument");
+  const Options o = get_options(dtype, n_fields);
+  if (option == HYDRO_OPT_WAVES_PER_SIMD) *value = o.waves_per_simd;
+  else if (option == HYDRO_OPT_XCD_REMAP) *value = o.xcd_remap;
+  else return fail(HYDRO_E_ARG, "hydro_get_option: unknown option %d", option);
+  return HYDRO_OK;
+}
 
 const char* hydro_last_error(void) { return error_buffer(); }
 

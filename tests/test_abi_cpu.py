@@ -126,12 +126,33 @@ def test_step_rejects_aliasing_and_flags_on_the_host(hb):
     assert lib.hydro_step(ctypes.byref(g), b, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
     assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 8, None) == hb.HYDRO_E_ARG
     assert lib.hydro_step(None, None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
-    g12 = _raw_grid(hb, n_fields=12)
-    assert lib.hydro_step(ctypes.byref(g12), None, a, b, a, 1.0, 0,
-                          None) == hb.HYDRO_E_UNSUPPORTED
     assert lib.hydro_rk3_step(ctypes.byref(g), a, b, b, a, 0.4, a, None) == hb.HYDRO_E_ARG
     assert lib.hydro_graph_launch(None, None) == hb.HYDRO_E_ARG
     assert lib.hydro_check_status(ctypes.byref(g), None) == hb.HYDRO_E_ARG
+
+
+def test_launch_options_roundtrip_and_validation(hb):
+    for dtype in (0, 1):
+        for nf in (6, 11, 16):
+            w0 = hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD)
+            hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD, 2)
+            assert hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD) == 2
+            hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD, w0)
+    for bad in ((0, 6, 1, 3), (0, 5, 1, 1), (2, 6, 1, 1), (0, 6, 9, 1), (1, 17, 2, 1),
+                (0, 6, 2, 5)):
+        with pytest.raises(hb.HydroError) as e:
+            hb.hydro_set_option(*bad)
+        assert e.value.code == hb.HYDRO_E_ARG
+
+
+def test_recorded_tuning_is_well_formed(hb):
+    import json
+    if not os.path.exists(hb.TUNING_PATH):
+        pytest.skip("no tuning recorded yet")
+    data = json.load(open(hb.TUNING_PATH))
+    for e in data["entries"]:
+        assert e["waves_per_simd"] in (1, 2) and e["xcd_remap"] in (0, 1)
+        assert 6 <= e["n_fields"] <= 16 and e["dtype"] in (0, 1)
 
 
 def test_product_path_has_no_oracle_dependency():

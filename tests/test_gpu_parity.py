@@ -317,3 +317,33 @@ def test_uneven_octree_22k_leaves_sampled(env):
 def test_turbulence_65k_leaves_sampled(env):
     w = inputs.config5()
     _sampled_rk3(env, w, 32, 5)
+
+
+@pytest.mark.parametrize("nf", [7, 16])
+@pytest.mark.parametrize("waves", [1, 2])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_every_register_budget_and_field_count(env, nf, waves, dtype):
+    """Both kernel register budgets, beyond the benchmark's field counts:
+    binary64 bit-exact against the oracle, binary32 within its rounding."""
+    torch, hb = env
+    w = inputs.blobs(base=2, max_level=2, threshold=0.5)
+    rng = np.random.default_rng(nf)
+    extra = [w.U[0] * rng.uniform(0.1, 0.3, size=w.U[0].shape) for _ in range(nf - 6)]
+    w.U = np.ascontiguousarray(np.concatenate([w.U[:6], np.stack(extra)]) if nf > 6 else w.U[:6])
+    grid, T, U = _setup(env, w, dtype=dtype)
+    old = hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD)
+    hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD, waves)
+    try:
+        dt_o = oracle.cfl_dt(T, w.U, 0.4)
+        dt = torch.tensor([dt_o], dtype=torch.float64, device="cuda")
+        out = grid.empty_state()
+        hb.hydro_step(grid, None, U, out, dt, 1.0)
+        ref, bad = oracle.step(T, w.U, dt_o)
+        got = out.double().cpu().numpy()
+        err = _rel(got, ref)
+        if dtype == 0:
+            assert np.array_equal(got, ref), err
+        else:
+            assert np.all(err < 1e-5), err
+    finally:
+        hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD, old)

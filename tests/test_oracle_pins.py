@@ -396,3 +396,75 @@ def test_cfl_closed_form_config2_first_step():
     T = _table(w)
     got = oracle.cfl_dt(T, w.U, 0.4) * (32 / 128)
     assert got == pytest.approx(want, rel=2e-4)
+
+
+# ----------------------------------------------------------------------------
+# coarse-fine flux correction
+# ----------------------------------------------------------------------------
+
+def _amr_case(nf=11, seed=3):
+    w = inputs.blobs(base=2, max_level=2, threshold=0.5)
+    s = inputs.random_smooth(w.leaf_coord, w.base, nf=nf, seed=seed, amp=0.2)
+    return w.leaf_coord, w.base, s.U
+
+
+def _volume_totals(coord, base, U):
+    dv = (1.0 / (8.0 * base * 2.0 ** coord[:, 0])) ** 3
+    return np.array([math.fsum((U[f] * dv[:, None, None, None]).ravel().tolist())
+                     for f in range(U.shape[0])])
+
+
+def test_reflux_makes_uneven_trees_conservative():
+    coord, base, U = _amr_case()
+    T = oracle.Table(coord, base)
+    assert (T.kind == oracle.SAME_REFINED).any() and (T.kind == oracle.COARSER_LEAF).any()
+    before = _volume_totals(coord, base, U)
+    scale = _volume_totals(coord, base, np.abs(U))
+    out, _, bad = oracle.rk3_step(T, U, 0.4, reflux=True)
+    assert bad == 0
+    drift = np.abs(_volume_totals(coord, base, out) - before) / scale
+    assert np.all(drift <= 1e-13), drift
+    # without the correction the same step is not conservative
+    out2, _, _ = oracle.rk3_step(T, U, 0.4, reflux=False)
+    drift2 = np.abs(_volume_totals(coord, base, out2) - before) / scale
+    assert drift2.max() > 1e-9, drift2
+
+
+def test_reflux_keeps_a_uniform_state_bit_identical():
+    coord, base, _ = _amr_case()
+    u = inputs.uniform_state(1, nf=11)
+    U = np.repeat(u.U[:, :1], len(coord), axis=1)
+    T = oracle.Table(coord, base)
+    out, _, _ = oracle.rk3_step(T, U, 0.4, reflux=True)
+    assert np.array_equal(out, U)
+
+
+def test_reflux_touches_only_coarse_cells_at_refined_faces():
+    coord, base, U = _amr_case(nf=6)
+    T = oracle.Table(coord, base)
+    dt = 0.2 * oracle.cfl_dt(T, U, 0.4)
+    out, ff, _ = oracle.step_record(T, U, dt)
+    corrected = oracle.reflux(T, out.copy(), dt, 1.0, ff)
+    changed = np.any((corrected != out).reshape(6, len(coord), 8, 8, 8), axis=0)
+    for n in range(len(coord)):
+        faces = [(d, side) for d in range(3) for side in range(2)
+                 if T.kind[n, 13 + (1 if side else -1) * (1, 3, 9)[d]] == oracle.SAME_REFINED]
+        allowed = np.zeros((8, 8, 8), bool)
+        for d, side in faces:
+            idx = [slice(None)] * 3
+            idx[2 - d] = 7 if side else 0
+            allowed[tuple(idx)] = True
+        assert not np.any(changed[n] & ~allowed), n
+        if faces:
+            assert changed[n].any(), n
+
+
+def test_recorded_face_fluxes_agree_across_same_level_faces():
+    # a face shared by two same-level leaves gets the same flux from both
+    base = 2
+    w = inputs.random_smooth(inputs.uniform_leaves(base), base, nf=6, seed=9)
+    T = oracle.Table(w.leaf_coord, base)
+    _, ff, _ = oracle.step_record(T, w.U, 1e-4)
+    for n in range(w.n_leaves):
+        m = T.nbr[n, 14]  # +x neighbour
+        assert np.array_equal(ff[n, 0, 1], ff[m, 0, 0])
