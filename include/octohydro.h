@@ -101,7 +101,48 @@ typedef struct hydro_grid {
   double gamma;            /* ratio of specific heats, e.g. 5.0/3.0        */
   double dual_energy_eta1; /* internal energy from tau when e < eta1 E;
                               <= 0 disables the switch                       */
+  /* Coarse-fine flux correction (Sec. V-B-1: fluxes are corrected on
+   * coarse-fine boundaries).  Optional: flux_reg_dev == NULL disables it.
+   * Tables from hydro_build_reflux; face orientation o = 2*axis + side.
+   *  face_slot_dev  int32 [n_leaves][6]: register slot of a coarse face whose
+   *                 neighbour is refined, or -1.
+   *  fine_slot_dev  int32 [n_leaves][6]: for a face whose neighbour is
+   *                 coarser, (slot << 2) | quadrant of the coarse face this
+   *                 fine face covers, or -1.
+   *  slot_leaf_dev  int32 [n_slots]: coarse leaf of each slot.
+   *  orient_begin   host int32 [7]: slots of orientation o are
+   *                 [orient_begin[o], orient_begin[o+1]).
+   *  flux_reg_dev   double [n_slots][n_fields][320]: caller-owned scratch
+   *                 (64 coarse fluxes, then the 16x16 fine fluxes). */
+  int32_t n_slots;
+  int32_t orient_begin[7];
+  const int32_t* face_slot_dev;
+  const int32_t* fine_slot_dev;
+  const int32_t* slot_leaf_dev;
+  double* flux_reg_dev;
+  /* Rotating frame (Sec. IV-C: the grid rotates with the binary's initial
+   * orbital frequency): angular velocity about the z axis through
+   * (0.5, 0.5).  0 = inertial frame.  Non-zero adds to L, per cell from Uk:
+   *   s_x: 2 omega s_y + rho omega^2 (x - 0.5)
+   *   s_y: rho omega^2 (y - 0.5) - 2 omega s_x
+   *   s_z: 0
+   *   E:   omega^2 (s_x (x - 0.5) + s_y (y - 0.5))                          */
+  double omega;
 } hydro_grid;
+
+/*
+ * Flux-register tables of a leaf list for the coarse-fine flux correction,
+ * on the host, from the outputs of hydro_build_table: face_slot and
+ * fine_slot [n_leaves][6], slot_leaf [max_slots], orient_begin [7] (all
+ * host, caller-owned).  A coarse leaf owns one slot per face that borders a
+ * refined block; slots are numbered by orientation, then leaf.  Returns
+ * HYDRO_E_TABLE if a fine face has no matching coarse face.  Synchronous,
+ * host only.
+ */
+int hydro_build_reflux(int32_t n_leaves, const int32_t* leaf_coord, const int32_t* nbr,
+                       const uint8_t* kind, int32_t* face_slot, int32_t* fine_slot,
+                       int32_t* slot_leaf, int32_t max_slots, int32_t* orient_begin,
+                       int32_t* n_slots_out);
 
 /*
  * Neighbour table of a leaf list (Sec. IV-C octree), on the host.
@@ -134,6 +175,11 @@ int hydro_fill_ghosts(const hydro_grid* grid, const void* U_dev, void* G_dev, vo
  *   Uout = U0 + beta * (t - U0)    otherwise.
  * The ghost fill is fused: each sub-grid reads its neighbours' cells
  * directly.  dt is read on the device from *dt_dev (binary64).
+ * With flux-register tables in the grid, the fluxes through coarse-fine
+ * faces are recorded and then corrected: each coarse cell next to a refined
+ * face gets q = (Havg - Hc)/dx with Havg = 0.25((H00 + H10) + (H01 + H11))
+ * of the 4 fine fluxes and Hc its own, and Uout -= w dt q on its high face,
+ * += on its low face (w = 1 without U0, else beta; faces x, y, z, low first).
  * Uout_dev may alias neither Uk_dev nor U0_dev.  flags: HYDRO_FLAG_VALIDATE.
  */
 int hydro_step(const hydro_grid* grid, const void* U0_dev, const void* Uk_dev, void* Uout_dev,

@@ -53,6 +53,7 @@ class _OGrid(ctypes.Structure):
         ("children", ctypes.c_void_p),
         ("gamma", ctypes.c_double),
         ("eta1", ctypes.c_double),
+        ("omega", ctypes.c_double),
     ]
 
 
@@ -142,8 +143,18 @@ class Table:
         return self.coord.shape[0]
 
 
+# Frame angular velocity used by every call (0: inertial frame).  Set with
+# set_omega(); rotating-frame sources (Sec. IV-C) are on when it is non-zero.
+_OMEGA = [0.0]
+
+
+def set_omega(omega: float) -> None:
+    _OMEGA[0] = float(omega)
+
+
 def _grid(table: Table, nf: int, gamma: float, eta1: float) -> _OGrid:
     g = _OGrid()
+    g.omega = _OMEGA[0]
     g.n_leaves = table.n_leaves
     g.nf = nf
     g.base = table.base

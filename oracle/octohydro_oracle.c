@@ -358,6 +358,32 @@ static void combine(int has_u0, double beta, double dt, double u0, double uk, do
   *out = has_u0 ? u0 + beta * (t - u0) : t;
 }
 
+/* Source of field f (1..4: s_x, s_y, s_z, E) in a frame rotating with
+ * angular velocity omega about the z axis through (0.5, 0.5) (Sec. IV-C: the
+ * grid rotates with the binary's initial orbital frequency): Coriolis
+ * -2 Omega x s and centrifugal rho Omega^2 r_perp on the momentum, and the
+ * centrifugal force's work Omega^2 (s . r_perp) on the energy; the Coriolis
+ * force does no work.  Evaluated from the cell values of Uk at the cell
+ * centre. */
+static double rotating_source(const ogrid* g, const double* Uk, int32_t n, int32_t cell, int f) {
+  const int32_t L = g->coord[4 * n + 0];
+  const double dx = 1.0 / (double)(SUB * (g->base << L));
+  const int32_t i = cell & 7, j = (cell >> 3) & 7;
+  const double rx = ((double)(SUB * g->coord[4 * n + 1] + i) + 0.5) * dx - 0.5;
+  const double ry = ((double)(SUB * g->coord[4 * n + 2] + j) + 0.5) * dx - 0.5;
+  const size_t fs = (size_t)g->n_leaves * CELLS;
+  const size_t at = (size_t)n * CELLS + cell;
+  const double rho = Uk[at], sx = Uk[fs + at], sy = Uk[2 * fs + at];
+  const double om2 = g->omega * g->omega;
+  const double tw = 2.0 * g->omega;
+  switch (f) {
+    case 1: return tw * sy + rho * om2 * rx;
+    case 2: return rho * om2 * ry - tw * sx;
+    case 4: return om2 * (sx * rx + sy * ry);
+    default: return 0.0;
+  }
+}
+
 /* Position of transverse cell (u, v) in a face normal to d: u, v are the
  * two other axes in increasing order (d=0: y,z; d=1: x,z; d=2: x,y). */
 static int32_t face_index(int32_t u, int32_t v) { return u + SUB * v; }
@@ -437,7 +463,9 @@ int64_t oracle_step_record(const ogrid* g, const double* U0, const double* Uk, d
       for (int f = 0; f < nf; ++f)
         for (int32_t cell = 0; cell < CELLS; ++cell) {
           const double* q = dH + (size_t)f * 3 * CELLS;
-          const double lrate = -((q[cell] + q[CELLS + cell]) + q[2 * CELLS + cell]) * inv_dx;
+          double lrate = -((q[cell] + q[CELLS + cell]) + q[2 * CELLS + cell]) * inv_dx;
+          if (g->omega != 0.0 && f >= 1 && f <= 4)
+            lrate = lrate + rotating_source(g, Uk, n, cell, f);
           const size_t at = ((size_t)f * g->n_leaves + n) * CELLS + cell;
           combine(U0 != NULL, beta, dt, U0 ? U0[at] : 0.0, Uk[at], lrate, &Uout[at]);
         }

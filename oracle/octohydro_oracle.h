@@ -19,6 +19,7 @@ typedef struct {
   const uint8_t* kind;     /* [n_leaves][27] */
   const int32_t* children; /* [n_nodes][8] */
   double gamma, eta1;
+  double omega; /* frame angular velocity about the z axis through (0.5, 0.5) */
 } ogrid;
 
 int oracle_build_table(int32_t n_leaves, int32_t base, const int32_t* leaf_coord, int32_t* nbr,

@@ -33,7 +33,7 @@ EXPORTS = [
     "hydro_build_table", "hydro_fill_ghosts", "hydro_step", "hydro_step_per_leaf",
     "hydro_cfl_dt", "hydro_totals", "hydro_rk3_step", "hydro_rk3_graph_create",
     "hydro_graph_launch", "hydro_graph_destroy", "hydro_check_status", "hydro_last_error",
-    "hydro_version", "hydro_set_option", "hydro_get_option",
+    "hydro_version", "hydro_set_option", "hydro_get_option", "hydro_build_reflux",
 ]
 HYDRO_OPT_WAVES_PER_SIMD, HYDRO_OPT_XCD_REMAP = 1, 2
 
@@ -59,6 +59,13 @@ class hydro_grid(ctypes.Structure):
         ("status_dev", ctypes.c_void_p),
         ("gamma", ctypes.c_double),
         ("dual_energy_eta1", ctypes.c_double),
+        ("n_slots", ctypes.c_int32),
+        ("orient_begin", ctypes.c_int32 * 7),
+        ("face_slot_dev", ctypes.c_void_p),
+        ("fine_slot_dev", ctypes.c_void_p),
+        ("slot_leaf_dev", ctypes.c_void_p),
+        ("flux_reg_dev", ctypes.c_void_p),
+        ("omega", ctypes.c_double),
     ]
 
 
@@ -85,6 +92,8 @@ def _load():
         "hydro_last_error": ([], ctypes.c_char_p),
         "hydro_version": ([], ctypes.c_int),
         "hydro_set_option": ([i32, i32, i32, i32], ctypes.c_int),
+        "hydro_build_reflux": ([i32, vp, vp, vp, vp, vp, vp, i32, vp, ctypes.POINTER(i32)],
+                               ctypes.c_int),
         "hydro_get_option": ([i32, i32, i32, ctypes.POINTER(i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -168,12 +177,33 @@ def hydro_build_table(leaf_coord: np.ndarray, base: int):
     return nbr, kind, np.ascontiguousarray(kids[: nn.value])
 
 
+def hydro_build_reflux(leaf_coord: np.ndarray, nbr: np.ndarray, kind: np.ndarray):
+    """Host flux-register tables: (face_slot [n][6], fine_slot [n][6],
+    slot_leaf [n_slots], orient_begin [7])."""
+    coord = np.ascontiguousarray(leaf_coord, dtype=np.int32)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    kind = np.ascontiguousarray(kind, dtype=np.uint8)
+    n = coord.shape[0]
+    face_slot = np.zeros((n, 6), np.int32)
+    fine_slot = np.zeros((n, 6), np.int32)
+    slot_leaf = np.zeros(6 * n, np.int32)
+    orient = np.zeros(7, np.int32)
+    ns = ctypes.c_int32(0)
+    _check(_lib.hydro_build_reflux(n, coord.ctypes.data, nbr.ctypes.data, kind.ctypes.data,
+                                   face_slot.ctypes.data, fine_slot.ctypes.data,
+                                   slot_leaf.ctypes.data, 6 * n, orient.ctypes.data,
+                                   ctypes.byref(ns)))
+    return face_slot, fine_slot, np.ascontiguousarray(slot_leaf[: ns.value]), orient
+
+
 class Grid:
     """A leaf batch resident on the GPU: the table in device memory plus the
-    hydro_grid struct that points at it."""
+    hydro_grid struct that points at it.  reflux=True also builds the
+    flux-register tables and scratch, which turns on the coarse-fine flux
+    correction."""
 
     def __init__(self, leaf_coord, base, n_fields, dtype=HYDRO_F64, gamma=5.0 / 3.0,
-                 eta1=1e-3, device="cuda"):
+                 eta1=1e-3, device="cuda", reflux=False, omega=0.0):
         coord = np.ascontiguousarray(leaf_coord, dtype=np.int32)
         nbr, kind, kids = hydro_build_table(coord, base)
         self.host_nbr, self.host_kind, self.host_children = nbr, kind, kids
@@ -193,7 +223,24 @@ class Grid:
             base=self.base, reserved=0, leaf_coord_dev=self.coord.data_ptr(),
             nbr_dev=self.nbr.data_ptr(), nbr_kind_dev=self.kind.data_ptr(),
             children_dev=self.children.data_ptr(), status_dev=self.status.data_ptr(),
-            gamma=float(gamma), dual_energy_eta1=float(eta1))
+            gamma=float(gamma), dual_energy_eta1=float(eta1), omega=float(omega))
+        self.reflux = bool(reflux)
+        if self.reflux:
+            fs, fi, sl, ob = hydro_build_reflux(coord, nbr, kind)
+            self.n_slots = len(sl)
+            if self.n_slots:
+                self.face_slot = torch.from_numpy(fs).to(dev)
+                self.fine_slot = torch.from_numpy(fi).to(dev)
+                self.slot_leaf = torch.from_numpy(sl).to(dev)
+                self.flux_reg = torch.empty((self.n_slots, self.n_fields, 320),
+                                            dtype=torch.float64, device=dev)
+                self.c.n_slots = self.n_slots
+                for i in range(7):
+                    self.c.orient_begin[i] = int(ob[i])
+                self.c.face_slot_dev = self.face_slot.data_ptr()
+                self.c.fine_slot_dev = self.fine_slot.data_ptr()
+                self.c.slot_leaf_dev = self.slot_leaf.data_ptr()
+                self.c.flux_reg_dev = self.flux_reg.data_ptr()
 
     @property
     def state_shape(self):

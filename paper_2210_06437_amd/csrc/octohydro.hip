@@ -57,7 +57,18 @@ struct GridArgs {
   int32_t* status;
   double gamma;
   double eta1;
+  // flux register (NULL: no coarse-fine flux correction)
+  const int32_t* face_slot;
+  const int32_t* fine_slot;
+  const int32_t* slot_leaf;
+  double* reg;
+  double omega;  // rotating-frame angular velocity (0: no sources)
 };
+
+// Values per register slot and field: 64 coarse face fluxes, then the 16x16
+// fine face fluxes that cover the same face.
+constexpr int REG_COARSE = 64;
+constexpr int REG_STRIDE = 64 + 256;
 
 __device__ __forceinline__ int wrap(int a, int m) {
   a = a < 0 ? a + m : a;
@@ -253,7 +264,30 @@ struct LeafInfo {
 // Face neighbour (kind, id) of a pencil axis, low and high side.
 struct FaceNbr {
   int klo, ilo, khi, ihi;
+  int rlo, rhi;  // coarse register slot of the low / high face, or -1
+  int flo, fhi;  // fine register entry (slot << 2 | quadrant), or -1
 };
+
+// Record the fluxes H (all fields) through face `face` (0 = low, 8 = high
+// face of the leaf) of a pencil at transverse position (u, v) of that face.
+template <typename T, int NF>
+__device__ __forceinline__ void record_face(const GridArgs& g, const FaceNbr& fn, int face, int u,
+                                            int v, const T (&H)[NF]) {
+  const int cs = face == 0 ? fn.rlo : fn.rhi;
+  const int fe = face == 0 ? fn.flo : fn.fhi;
+  if (cs >= 0) {
+    double* r = g.reg + (size_t)cs * NF * REG_STRIDE + u + 8 * v;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) r[f * REG_STRIDE] = (double)H[f];
+  }
+  if (fe >= 0) {
+    const int q = fe & 3;
+    double* r = g.reg + (size_t)(fe >> 2) * NF * REG_STRIDE + REG_COARSE +
+                (8 * (q & 1) + u) + 16 * (8 * (q >> 1) + v);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) r[f * REG_STRIDE] = (double)H[f];
+  }
+}
 
 // A lane's pencil along axis d through transverse cell (a, b): where each of
 // its 14 stream values comes from.  Interior values sit at off + (k-3) sd in
@@ -393,8 +427,10 @@ __device__ __forceinline__ void core_flux(const Phys<T>& ph, int d, const T (&UL
 // t (first stage) or U0 + beta (t - U0).
 template <typename T>
 __device__ __forceinline__ void finish_cell(const StepArgs& s, size_t fbase, uint32_t cell, T uk,
-                                            double sum, double dt, double inv_dx) {
-  const double lrate = -sum * inv_dx;
+                                            double sum, bool has_src, double src, double dt,
+                                            double inv_dx) {
+  double lrate = -sum * inv_dx;
+  if (has_src) lrate = lrate + src;
   const double t = (double)uk + dt * lrate;
   double out;
   if (s.U0) {
@@ -508,6 +544,7 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
     }
     T H[NF];
     stream_step<T, NF>(ph, d, st, qn, H, bad);
+    if (g.reg && (k == 5 || k == TW - 1)) record_face<T, NF>(g, fn, k - 5, a, 4 * h + zz, H);
     if (k >= 6) {
       const int i = k - 6;  // interior cell along d: H now is its high face
       const bool first = d == 0 ? i <= a : i < a;
@@ -568,13 +605,28 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
     }
     T H[NF];
     stream_step<T, NF>(ph, 2, st, qn, H, bad);
+    if (g.reg && (k == 5 || k == TW - 1)) record_face<T, NF>(g, fn, k - 5, x, y, H);
     if (kk >= 6) {
       const int i = k - 6;  // interior cell along z
       const int ai = (i - k0) * ACC_PLANE + y * ACC_PITCH + x;
+      // rotating-frame sources of s_x, s_y, s_z, E from this cell's Uk
+      double src[4] = {0.0, 0.0, 0.0, 0.0};
+      const bool rot = g.omega != 0.0;
+      if (rot) {
+        const double dx = 1.0 / (double)(SUB * li.blocks);
+        const double rx = ((double)(SUB * li.ix + x) + 0.5) * dx - 0.5;
+        const double ry = ((double)(SUB * li.iy + y) + 0.5) * dx - 0.5;
+        const double rho = (double)st[0].qy, sx = (double)st[1].qy, sy = (double)st[2].qy;
+        const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+        src[0] = tw * sy + rho * om2 * rx;
+        src[1] = rho * om2 * ry - tw * sx;
+        src[3] = om2 * (sx * rx + sy * ry);
+      }
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         const double sum = acc[f * ACC_HALF + ai] + ((double)H[f] - Hprev[f]);
-        finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, st[f].qy, sum, dt, inv_dx);
+        finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, st[f].qy, sum,
+                       rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
       }
     }
 #pragma unroll
@@ -619,6 +671,21 @@ __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
   fz.ilo = nb[4];
   fz.khi = kd[22];
   fz.ihi = nb[22];
+  fxy.rlo = fxy.rhi = fxy.flo = fxy.fhi = -1;
+  fz.rlo = fz.rhi = fz.flo = fz.fhi = -1;
+  if (g.reg) {
+    // register slots per face orientation o = 2*axis + side
+    const int32_t* fsl = g.face_slot + 6 * leaf;
+    const int32_t* fin = g.fine_slot + 6 * leaf;
+    fxy.rlo = xlane ? fsl[0] : fsl[2];
+    fxy.rhi = xlane ? fsl[1] : fsl[3];
+    fxy.flo = xlane ? fin[0] : fin[2];
+    fxy.fhi = xlane ? fin[1] : fin[3];
+    fz.rlo = fsl[4];
+    fz.rhi = fsl[5];
+    fz.flo = fin[4];
+    fz.fhi = fin[5];
+  }
   const double dt = *s.dt;
   const double inv_dx = (double)(SUB * li.blocks);
   Phys<T> ph;
@@ -635,6 +702,42 @@ __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
     __builtin_amdgcn_wave_barrier();
   }
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-fine flux correction: one launch per face orientation o, one thread
+// per (slot, field, coarse face cell); a coarse leaf has at most one slot per
+// orientation, so no two threads of a launch touch the same value.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_reflux(GridArgs g, T* __restrict__ Uout, const double* dt, double w, int o, int s0,
+             int n_in_orient) {
+  const int64_t total = (int64_t)n_in_orient * g.nf * 64;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int uv = (int)(idx & 63);
+  const int64_t sf = idx >> 6;
+  const int f = (int)(sf % g.nf);
+  const int slot = s0 + (int)(sf / g.nf);
+  const int u = uv & 7, v = uv >> 3;
+  const int c = g.slot_leaf[slot];
+  const double inv_dx = (double)(SUB * (g.base << g.coord[4 * c]));
+  const double* r = g.reg + ((size_t)slot * g.nf + f) * REG_STRIDE;
+  const double hc = r[u + 8 * v];
+  const double* fr = r + REG_COARSE + 2 * u + 16 * (2 * v);
+  const double havg = 0.25 * ((fr[0] + fr[1]) + (fr[16] + fr[17]));
+  const double q = (havg - hc) * inv_dx;
+  const double wdt = w * *dt;
+  const int d = o >> 1, side = o & 1;
+  int l[3];
+  l[d] = side ? SUB - 1 : 0;
+  l[d == 0 ? 1 : 0] = u;
+  l[d == 2 ? 1 : 2] = v;
+  T* out = Uout + ((size_t)f * g.n_leaves + c) * CELLS + l[2] * 64 + l[1] * 8 + l[0];
+  const double val = (double)*out;
+  *out = (T)(side ? val - wdt * q : val + wdt * q);
 }
 
 // ---------------------------------------------------------------------------
@@ -807,6 +910,15 @@ static int check_grid(const hydro_grid* gr, const char* fn) {
   if (gr->n_nodes > 0 && !gr->children_dev)
     return fail(HYDRO_E_ARG, "%s: children_dev is NULL but n_nodes > 0", fn);
   if (!(gr->gamma > 1.0)) return fail(HYDRO_E_ARG, "%s: gamma must exceed 1", fn);
+  if (gr->flux_reg_dev && gr->n_slots > 0) {
+    if (!gr->face_slot_dev || !gr->fine_slot_dev || !gr->slot_leaf_dev)
+      return fail(HYDRO_E_ARG, "%s: flux register set but its tables are not", fn);
+    if (gr->orient_begin[0] != 0 || gr->orient_begin[6] != gr->n_slots)
+      return fail(HYDRO_E_ARG, "%s: orient_begin does not span the slots", fn);
+    for (int o = 0; o < 6; ++o)
+      if (gr->orient_begin[o + 1] < gr->orient_begin[o])
+        return fail(HYDRO_E_ARG, "%s: orient_begin is not ascending", fn);
+  }
   return HYDRO_OK;
 }
 
@@ -823,7 +935,33 @@ static GridArgs grid_args(const hydro_grid* gr) {
   g.status = gr->status_dev;
   g.gamma = gr->gamma;
   g.eta1 = gr->dual_energy_eta1;
+  const bool reflux = gr->flux_reg_dev != nullptr && gr->n_slots > 0;
+  g.face_slot = reflux ? gr->face_slot_dev : nullptr;
+  g.fine_slot = reflux ? gr->fine_slot_dev : nullptr;
+  g.slot_leaf = reflux ? gr->slot_leaf_dev : nullptr;
+  g.reg = reflux ? gr->flux_reg_dev : nullptr;
+  g.omega = gr->omega;
   return g;
+}
+
+// The flux-correction launches after a substep (nothing without tables).
+static int reflux_launch(const hydro_grid* gr, const StepArgs& a, hipStream_t st) {
+  if (!a.g.reg) return HYDRO_OK;
+  const double w = a.U0 ? a.beta : 1.0;
+  for (int o = 0; o < 6; ++o) {
+    const int s0 = gr->orient_begin[o], n = gr->orient_begin[o + 1] - s0;
+    if (n <= 0) continue;
+    const int64_t total = (int64_t)n * a.g.nf * 64;
+    const int blocks = (int)((total + 255) / 256);
+    if (gr->dtype == HYDRO_F64)
+      hipLaunchKernelGGL(k_reflux<double>, dim3(blocks), dim3(256), 0, st, a.g,
+                         static_cast<double*>(a.Uout), a.dt, w, o, s0, n);
+    else
+      hipLaunchKernelGGL(k_reflux<float>, dim3(blocks), dim3(256), 0, st, a.g,
+                         static_cast<float*>(a.Uout), a.dt, w, o, s0, n);
+    HIP_TRY(hipGetLastError());
+  }
+  return HYDRO_OK;
 }
 
 static int grid_blocks(int64_t work, int threads, int cap) {
@@ -947,15 +1085,18 @@ static int rk3_launch(const hydro_grid* gr, const void* Un, void* W1, void* W2, 
   rc = step_common(gr, nullptr, Un, W1, dt, 1.0, 0, "hydro_rk3_step", a);
   if (rc) return rc;
   HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
+  if ((rc = reflux_launch(gr, a, st))) return rc;
   a.U0 = Un;
   a.Uk = W1;
   a.Uout = W2;
   a.beta = 0.25;
   HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
+  if ((rc = reflux_launch(gr, a, st))) return rc;
   a.Uk = W2;
   a.Uout = Unext;
   a.beta = 2.0 / 3.0;
   HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
+  if ((rc = reflux_launch(gr, a, st))) return rc;
   return HYDRO_OK;
 }
 
@@ -1074,7 +1215,7 @@ int hydro_step(const hydro_grid* gr, const void* U0, const void* Uk, void* Uout,
     if (rc) return rc;
   }
   HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
-  return HYDRO_OK;
+  return reflux_launch(gr, a, st);
 }
 
 int hydro_step_per_leaf(const hydro_grid* gr, const void* U0, const void* Uk, void* Uout,
@@ -1116,7 +1257,7 @@ int hydro_step_per_leaf(const hydro_grid* gr, const void* U0, const void* Uk, vo
     HIP_TRY(hipEventRecord(g_pool.events[i], g_pool.streams[i]));
     HIP_TRY(hipStreamWaitEvent(st, g_pool.events[i], 0));
   }
-  return HYDRO_OK;
+  return reflux_launch(gr, a, st);
 }
 
 int hydro_cfl_dt(const hydro_grid* gr, const void* U, double cfl, double* dt, void* stream) {

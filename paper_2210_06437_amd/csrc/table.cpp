@@ -103,3 +103,61 @@ extern "C" int hydro_build_table(int32_t n_leaves, int32_t base, const int32_t* 
   *n_nodes_out = n_nodes;
   return HYDRO_OK;
 }
+
+// Flux-register tables for the coarse-fine flux correction.  Face
+// orientation o = 2*d + side (d = axis, side 0 = low face, 1 = high face).
+// A coarse leaf whose face o borders a refined block owns one register slot
+// for that face; slots are numbered orientation by orientation, leaves
+// ascending within one orientation.  A fine leaf whose face o borders a
+// coarser leaf writes its fluxes into the coarse leaf's slot for the
+// opposite face, in the quadrant given by its coordinate parities along the
+// face's two axes (u, v in increasing axis order).
+extern "C" int hydro_build_reflux(int32_t n_leaves, const int32_t* leaf_coord,
+                                  const int32_t* nbr, const uint8_t* kind,
+                                  int32_t* face_slot, int32_t* fine_slot, int32_t* slot_leaf,
+                                  int32_t max_slots, int32_t* orient_begin,
+                                  int32_t* n_slots_out) {
+  octohydro::clear_error();
+  if (n_leaves <= 0 || !leaf_coord || !nbr || !kind || !face_slot || !fine_slot || !slot_leaf ||
+      !orient_begin || !n_slots_out || max_slots < 0)
+    return octohydro::fail(HYDRO_E_ARG, "hydro_build_reflux: bad argument");
+  // face orientation o -> slot of the face neighbour in the 27-slot table
+  auto nslot = [](int o) {
+    const int d = o >> 1, s = (o & 1) ? 1 : -1;
+    int r[3] = {0, 0, 0};
+    r[d] = s;
+    return (r[2] + 1) * 9 + (r[1] + 1) * 3 + (r[0] + 1);
+  };
+  int32_t n_slots = 0;
+  for (int o = 0; o < 6; ++o) {
+    orient_begin[o] = n_slots;
+    for (int32_t i = 0; i < n_leaves; ++i) {
+      face_slot[6 * i + o] = -1;
+      if (kind[27 * i + nslot(o)] == HYDRO_SAME_REFINED) {
+        if (n_slots >= max_slots)
+          return octohydro::fail(HYDRO_E_ARG, "hydro_build_reflux: more than %d slots",
+                                 max_slots);
+        slot_leaf[n_slots] = i;
+        face_slot[6 * i + o] = n_slots++;
+      }
+    }
+  }
+  orient_begin[6] = n_slots;
+  for (int32_t i = 0; i < n_leaves; ++i)
+    for (int o = 0; o < 6; ++o) {
+      fine_slot[6 * i + o] = -1;
+      if (kind[27 * i + nslot(o)] != HYDRO_COARSER_LEAF) continue;
+      const int32_t c = nbr[27 * i + nslot(o)];
+      const int32_t cs = (c >= 0 && c < n_leaves) ? face_slot[6 * c + (o ^ 1)] : -1;
+      if (cs < 0)
+        return octohydro::fail(HYDRO_E_TABLE,
+                               "hydro_build_reflux: leaf %d face %d has no matching coarse face",
+                               i, o);
+      const int d = o >> 1;
+      const int au = d == 0 ? 1 : 0, av = d == 2 ? 1 : 2;  // axes u < v other than d
+      const int qu = leaf_coord[4 * i + 1 + au] & 1, qv = leaf_coord[4 * i + 1 + av] & 1;
+      fine_slot[6 * i + o] = (cs << 2) | (qu + 2 * qv);
+    }
+  *n_slots_out = n_slots;
+  return HYDRO_OK;
+}

@@ -162,3 +162,31 @@ def test_product_path_has_no_oracle_dependency():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "octohydro_oracle" not in text, f
+
+
+@pytest.mark.parametrize("which", [2, 3])
+def test_flux_register_tables_are_consistent(hb, which):
+    coord, base = list(_trees())[which]
+    nbr, kind, kids = hb.hydro_build_table(coord, base)
+    fs, fi, sl, ob = hb.hydro_build_reflux(coord, nbr, kind)
+    n = len(coord)
+    assert ob[0] == 0 and ob[6] == len(sl) and np.all(np.diff(ob) >= 0)
+    face_nbr = [12, 14, 10, 16, 4, 22]  # 27-slot of face orientation o = 2*axis + side
+    cover = {}
+    for i in range(n):
+        for o in range(6):
+            k = kind[i, face_nbr[o]]
+            assert (fs[i, o] >= 0) == (k == hb.HYDRO_SAME_REFINED)
+            assert (fi[i, o] >= 0) == (k == hb.HYDRO_COARSER_LEAF)
+            if fs[i, o] >= 0:
+                s = fs[i, o]
+                assert sl[s] == i and ob[o] <= s < ob[o + 1]
+            if fi[i, o] >= 0:
+                s, q = fi[i, o] >> 2, fi[i, o] & 3
+                assert sl[s] == nbr[i, face_nbr[o]]  # the coarse neighbour owns the slot
+                assert ob[o ^ 1] <= s < ob[(o ^ 1) + 1]  # ... on its opposite face
+                cover.setdefault(s, []).append(q)
+    # every coarse slot is covered by exactly four fine quadrants
+    assert sorted(cover) == list(range(len(sl)))
+    for s, qs in cover.items():
+        assert sorted(qs) == [0, 1, 2, 3], (s, qs)

@@ -347,3 +347,105 @@ def test_every_register_budget_and_field_count(env, nf, waves, dtype):
             assert np.all(err < 1e-5), err
     finally:
         hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD, old)
+
+
+REFLUX_CASES = [("amr-base2-levels0-2", inputs.blobs(base=2, max_level=2, threshold=0.5)),
+                ("amr-base4-levels0-3", inputs.blobs(base=4, max_level=3))]
+
+
+@pytest.mark.parametrize("name,w", REFLUX_CASES, ids=[c[0] for c in REFLUX_CASES])
+def test_rk3_with_flux_correction_matches_oracle(env, name, w):
+    torch, hb = env
+    grid = hb.Grid(w.leaf_coord, w.base, w.nf, hb.HYDRO_F64, reflux=True)
+    assert grid.n_slots > 0
+    T = oracle.Table(w.leaf_coord, w.base)
+    U = torch.from_numpy(w.U).to("cuda")
+    W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    tot0 = torch.zeros(w.nf, dtype=torch.float64, device="cuda")
+    hb.hydro_totals(grid, U, tot0)
+    Uo = w.U
+    for step in range(2):
+        hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.4, dt)
+        Uo, dto, bad = oracle.rk3_step(T, Uo, 0.4, reflux=True)
+        assert bad == 0 and dt.item() == dto
+        got = Un.cpu().numpy()
+        err = _rel(got, Uo)
+        print(f"  {name} step {step}: rel err {err.max():.3e} bit-exact {np.array_equal(got, Uo)}")
+        assert np.all(err <= TOL64), err
+        U, Un = Un, U
+    tot = torch.zeros(w.nf, dtype=torch.float64, device="cuda")
+    hb.hydro_totals(grid, U, tot)
+    # scale: sum of |q| dV over the larger of the initial and final states
+    # (s_x and s_z start at zero here)
+    dv = (1.0 / (8.0 * w.base * 2.0 ** w.leaf_coord[:, 0])) ** 3
+    big = np.maximum(np.abs(w.U), np.abs(U.cpu().numpy()))
+    scale = (big * dv[None, :, None, None, None]).reshape(w.nf, -1).sum(1)
+    drift = np.abs(tot.cpu().numpy() - tot0.cpu().numpy()) / scale
+    print(f"  {name} conservation with flux correction: {drift.max():.2e}")
+    assert np.all(drift <= 1e-13), drift
+
+
+def test_uneven_octree_22k_leaves_with_flux_correction_sampled(env):
+    """The 21988-leaf octree with the correction on: one graph-captured RK3
+    step, checked on sampled leaves (the oracle evaluates each stage on the
+    rings of leaves the samples depend on)."""
+    torch, hb = env
+    w = inputs.config3()
+    grid = hb.Grid(w.leaf_coord, w.base, w.nf, hb.HYDRO_F64, reflux=True)
+    T = oracle.Table(w.leaf_coord, w.base)
+    U = torch.from_numpy(w.U).to("cuda")
+    W1, W2 = grid.empty_state(), grid.empty_state()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g = hb.Rk3Graph(grid, U, W1, W2, W1, 0.4, dt)
+    g.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(33)
+    S = np.unique(rng.choice(w.n_leaves, 40, replace=False).astype(np.int32))
+    # leaves next to coarse-fine faces are the interesting ones
+    near = np.nonzero((T.kind == oracle.SAME_REFINED).any(1))[0]
+    S = np.unique(np.concatenate([S, rng.choice(near, 16, replace=False)]).astype(np.int32))
+    R1 = oracle.neighbours(T, S)
+    R2 = oracle.neighbours(T, R1)
+    R3 = oracle.neighbours(T, R2)
+    dto = oracle.cfl_dt(T, w.U, 0.4)
+    assert dt.item() == dto
+    o1, ff, _ = oracle.step_record(T, w.U, dto, leaves=R3)
+    oracle.reflux(T, o1, dto, 1.0, ff, leaves=R2)
+    o2, ff, _ = oracle.step_record(T, o1, dto, beta=0.25, U0=w.U, leaves=R2)
+    oracle.reflux(T, o2, dto, 0.25, ff, leaves=R1)
+    o3, ff, _ = oracle.step_record(T, o2, dto, beta=2.0 / 3.0, U0=w.U, leaves=R1)
+    oracle.reflux(T, o3, dto, 2.0 / 3.0, ff, leaves=S)
+    got = W1.cpu().numpy()[:, S]
+    want = o3[:, S]
+    err = _rel(got, want)
+    print(f"config3 + flux correction: {len(S)} samples, rel err {err.max():.3e}, "
+          f"bit-exact {np.array_equal(got, want)}")
+    assert np.all(err <= TOL64), err
+    g.close()
+
+
+@pytest.mark.parametrize("reflux", [False, True])
+def test_rotating_frame_sources_match_oracle(env, reflux):
+    torch, hb = env
+    om = 0.9
+    w = (inputs.blobs(base=2, max_level=2, threshold=0.5) if reflux else
+         inputs.random_smooth(inputs.uniform_leaves(2), 2, nf=11, seed=5, amp=0.1))
+    grid = hb.Grid(w.leaf_coord, w.base, w.nf, hb.HYDRO_F64, reflux=reflux, omega=om)
+    T = oracle.Table(w.leaf_coord, w.base)
+    U = torch.from_numpy(w.U).to("cuda")
+    W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.4, dt)
+    oracle.set_omega(om)
+    try:
+        ref, dto, _ = oracle.rk3_step(T, w.U, 0.4, reflux=reflux)
+    finally:
+        oracle.set_omega(0.0)
+    got = Un.cpu().numpy()
+    err = _rel(got, ref)
+    print(f"  rotating frame (reflux={reflux}): rel err {err.max():.3e} "
+          f"bit-exact {np.array_equal(got, ref)}")
+    assert np.all(err <= TOL64), err
+    inert, _, _ = oracle.rk3_step(T, w.U, 0.4, reflux=reflux)
+    assert not np.array_equal(ref, inert)  # the sources act

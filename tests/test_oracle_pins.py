@@ -468,3 +468,63 @@ def test_recorded_face_fluxes_agree_across_same_level_faces():
     for n in range(w.n_leaves):
         m = T.nbr[n, 14]  # +x neighbour
         assert np.array_equal(ff[n, 0, 1], ff[m, 0, 0])
+
+
+# ----------------------------------------------------------------------------
+# rotating-frame sources
+# ----------------------------------------------------------------------------
+
+@pytest.fixture
+def rotating():
+    def set_(om):
+        oracle.set_omega(om)
+    yield set_
+    oracle.set_omega(0.0)
+
+
+def test_zero_frame_rotation_is_the_inertial_step(rotating):
+    w = inputs.random_smooth(inputs.uniform_leaves(2), 2, nf=6, seed=21)
+    T = oracle.Table(w.leaf_coord, 2)
+    a, _ = oracle.step(T, w.U, 1e-3)
+    rotating(0.0)
+    b, _ = oracle.step(T, w.U, 1e-3)
+    assert np.array_equal(a, b)
+
+
+def test_centrifugal_and_coriolis_accelerations_on_a_uniform_state(rotating):
+    # uniform state: every flux difference vanishes, so one forward-Euler
+    # substep changes s by dt * (-2 Omega x s + rho Omega^2 r_perp) and E by
+    # dt * Omega^2 (s . r_perp): the rotating-frame accelerations
+    om, dt = 0.7, 1e-3
+    w = inputs.uniform_state(2, nf=6, rho=1.3, v=(0.2, -0.1, 0.05), p=0.9)
+    T = oracle.Table(w.leaf_coord, 2)
+    rotating(om)
+    out, _ = oracle.step(T, w.U, dt)
+    X, Y, _ = inputs.cell_centres(w.leaf_coord, 2)
+    rx, ry = X - 0.5, Y - 0.5
+    rho, sx, sy = w.U[0], w.U[1], w.U[2]
+    np.testing.assert_allclose(out[1] - sx, dt * (2 * om * sy + rho * om * om * rx), rtol=1e-9,
+                               atol=1e-16)
+    np.testing.assert_allclose(out[2] - sy, dt * (-2 * om * sx + rho * om * om * ry), rtol=1e-9,
+                               atol=1e-16)
+    np.testing.assert_allclose(out[4] - w.U[4], dt * om * om * (sx * rx + sy * ry), rtol=1e-8,
+                               atol=1e-16)
+    assert np.array_equal(out[0], w.U[0]) and np.array_equal(out[3], w.U[3])
+    assert np.array_equal(out[5], w.U[5])
+
+
+def test_coriolis_force_does_no_work(rotating):
+    # on the rotation axis the centrifugal terms vanish; the Coriolis change
+    # of momentum is perpendicular to the momentum
+    om, dt = 1.1, 1e-3
+    w = inputs.uniform_state(2, nf=6, v=(0.3, 0.4, 0.0))
+    T = oracle.Table(w.leaf_coord, 2)
+    rotating(om)
+    out, _ = oracle.step(T, w.U, dt)
+    X, Y, _ = inputs.cell_centres(w.leaf_coord, 2)
+    rx, ry = X - 0.5, Y - 0.5
+    cor_x = out[1] - w.U[1] - dt * w.U[0] * om * om * rx
+    cor_y = out[2] - w.U[2] - dt * w.U[0] * om * om * ry
+    dot = cor_x * w.U[1] + cor_y * w.U[2]
+    assert np.abs(dot).max() < 1e-15
+    np.testing.assert_allclose(np.hypot(cor_x, cor_y), 2 * om * dt * 0.5, rtol=1e-6)
