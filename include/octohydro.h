@@ -24,6 +24,9 @@
  *  - State arrays are structure-of-arrays [n_fields][n_leaves][8][8][8] with x
  *    fastest, in the element type named by hydro_grid.dtype.  Ghosted tiles
  *    are [n_fields][n_leaves][14][14][14] (interior at [3,11)^3).
+ *  - n_leaves is at most HYDRO_MAX_LEAVES, so that one field array of a
+ *    state stays below 4 GiB (kernels address it with 32-bit byte offsets);
+ *    larger grids are rejected with HYDRO_E_ARG.
  *  - The domain is the periodic unit cube; a leaf at level L with coordinates
  *    (ix,iy,iz) covers level-L cells [8 ix, 8 ix + 8) x ... of width
  *    1 / (8 base 2^L).
@@ -86,6 +89,8 @@ extern "C" {
  *  status_dev      int32, or NULL: kernels OR status bits into it.
  * The tree must be 2:1 balanced over all 26 neighbours ("properly nested").
  */
+#define HYDRO_MAX_LEAVES 1048575
+
 typedef struct hydro_grid {
   int32_t n_leaves;
   int32_t n_nodes;

@@ -290,12 +290,13 @@ __device__ __forceinline__ void record_face(const GridArgs& g, const FaceNbr& fn
 }
 
 // A lane's pencil along axis d through transverse cell (a, b): where each of
-// its 14 stream values comes from.  Interior values sit at off + (k-3) sd in
-// the leaf; each ghost value k in {0,1,2,11,12,13} comes from the element
-// offset gofs[] of the field array -- a same-level cell, the covering coarse
-// cell (injection), or, on a refined side, the first of the 8 fine cells it
-// averages, which lie at +{0,1,8,9,64,65,72,73}.  The sources are the same
-// for every field, so they are worked out once per pencil.
+// its 14 stream values comes from, as byte offsets into a field array.
+// Interior value k sits at off + (k-3) sd; each ghost value k in
+// {0,1,2,11,12,13} comes from gofs[] -- a same-level cell, the covering
+// coarse cell (injection), or, on a refined side, the first of the 8 fine
+// cells it averages, which lie at +{0,1,8,9,64,65,72,73} elements.  The
+// sources are the same for every field, so they are worked out once per
+// pencil.
 typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
 
 struct Pencil {
@@ -319,12 +320,14 @@ __device__ __forceinline__ uint32_t ghost_offset(const GridArgs& g, const LeafIn
   return child * CELLS + ((2 * lz) & 7) * 64 + ((2 * ly) & 7) * 8 + ((2 * lx) & 7);
 }
 
+template <typename T>
 __device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo& li, int d, int a,
                                               int b, const FaceNbr& fn) {
   Pencil p;
+  constexpr uint32_t W = sizeof(T);
   // d = 0: (x, a=y, b=z); d = 1: (a=x, y, b=z); d = 2: (a=x, b=y, z)
-  p.off = li.leaf * CELLS + (d == 0 ? b * 64 + a * 8 : (d == 1 ? b * 64 + a : b * 8 + a));
-  p.sd = d == 0 ? 1 : (d == 1 ? 8 : 64);
+  p.off = W * (li.leaf * CELLS + (d == 0 ? b * 64 + a * 8 : (d == 1 ? b * 64 + a : b * 8 + a)));
+  p.sd = W * (d == 0 ? 1 : (d == 1 ? 8 : 64));
   const int klo = fn.klo, ilo = fn.ilo, khi = fn.khi, ihi = fn.ihi;
   p.ref_lo = klo == HYDRO_SAME_REFINED;
   p.ref_hi = khi == HYDRO_SAME_REFINED;
@@ -335,15 +338,12 @@ __device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo&
     const int lx = d == 0 ? l : a;
     const int ly = d == 0 ? a : (d == 1 ? l : b);
     const int lz = d == 2 ? l : b;
-    p.gofs[j] = ghost_offset(g, li, hi ? khi : klo, hi ? ihi : ilo, hi ? 1 : -1, d, lx, ly, lz);
+    p.gofs[j] =
+        W * ghost_offset(g, li, hi ? khi : klo, hi ? ihi : ilo, hi ? 1 : -1, d, lx, ly, lz);
   }
   return p;
 }
 
-// Value at stream position k (0..13) of a lane's pencil in field array Uf.
-#ifndef OCTOHYDRO_GOFS_CHAIN
-#define OCTOHYDRO_GOFS_CHAIN 0
-#endif
 #ifndef OCTOHYDRO_FENCE_RESTRICT
 #define OCTOHYDRO_FENCE_RESTRICT 0
 #endif
@@ -367,27 +367,68 @@ __device__ __forceinline__ void st(T* __restrict__ base, uint32_t off, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T))) = v;
 }
 
-// Uf is the field's base address (the same for every lane); all per-lane
-// addressing is a 32-bit element offset from it.
-template <typename T>
-__device__ __forceinline__ T pencil_value(const T* __restrict__ Uf, const Pencil& p, int k) {
-  if (k >= GH && k < GH + SUB) return ld(Uf, p.off + (uint32_t)(k - GH) * p.sd);
-#if OCTOHYDRO_GOFS_CHAIN
-  const uint32_t go = k == 0 ? p.gofs[0] : k == 1 ? p.gofs[1] : k == 2 ? p.gofs[2]
-                    : k == 11 ? p.gofs[3] : k == 12 ? p.gofs[4] : p.gofs[5];
-#else
-  const uint32_t go = p.gofs[k < GH ? k : k - SUB];
-#endif
-  T v;
-  if (k < GH ? p.ref_lo : p.ref_hi) {
-    OCTOHYDRO_RFENCE();
-    v = T(0.125) * (((ld(Uf, go) + ld(Uf, go + 1u)) + (ld(Uf, go + 8u) + ld(Uf, go + 9u))) +
-                    ((ld(Uf, go + 64u) + ld(Uf, go + 65u)) + (ld(Uf, go + 72u) + ld(Uf, go + 73u))));
-    OCTOHYDRO_RFENCE();
-  } else {
-    v = ld(Uf, go);
+// Where stream position k (0..13) of a pencil comes from: a byte offset
+// into a field array and whether it is a refined ghost (mean of 8 cells).
+// Worked out once per stream step and shared by every field; for a step
+// index known only at run time the ghost offset is picked by a select chain
+// over the six values.
+struct Src {
+  uint32_t o;
+  bool ref;
+};
+
+__device__ __forceinline__ Src pencil_src(const Pencil& p, int k) {
+  Src s;
+  if (k >= GH && k < GH + SUB) {
+    s.o = p.off + (uint32_t)(k - GH) * p.sd;
+    s.ref = false;
+    return s;
   }
-  return v;
+  s.o = k == 0 ? p.gofs[0] : k == 1 ? p.gofs[1] : k == 2 ? p.gofs[2]
+      : k == 11 ? p.gofs[3] : k == 12 ? p.gofs[4] : p.gofs[5];
+  s.ref = k < GH ? p.ref_lo : p.ref_hi;
+  return s;
+}
+
+// Buffer view of a state array: a 128-bit resource (base address, size)
+// held in scalar registers.  A load names the field by a scalar byte offset
+// (f times the field stride) and the cell by a 32-bit lane byte offset plus
+// a small immediate, so no 64-bit per-lane address is ever formed.  The
+// whole array must stay below 4 GiB (checked on the host).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int RSRC_WORD3 = 0x00020000;  // raw dword data format (gfx9 family)
+
+__device__ __forceinline__ Rsrc state_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, -1, RSRC_WORD3);
+}
+
+// Field view: the array's resource and the field's scalar byte offset.
+struct FieldView {
+  Rsrc r;
+  uint32_t fo;
+};
+
+__device__ __forceinline__ double bload(double, const FieldView& v, uint32_t o) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(v.r, (int)o, (int)v.fo, 0));
+}
+__device__ __forceinline__ float bload(float, const FieldView& v, uint32_t o) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v.r, (int)o, (int)v.fo, 0));
+}
+
+// The value a stream position takes in one field.
+template <typename T>
+__device__ __forceinline__ T src_value(const FieldView& v, Src s) {
+  constexpr uint32_t W = sizeof(T);
+  if (s.ref) {
+    OCTOHYDRO_RFENCE();
+    const T r = T(0.125) * (((bload(T(), v, s.o) + bload(T(), v, s.o + W)) +
+                             (bload(T(), v, s.o + 8 * W) + bload(T(), v, s.o + 9 * W))) +
+                            ((bload(T(), v, s.o + 64 * W) + bload(T(), v, s.o + 65 * W)) +
+                             (bload(T(), v, s.o + 72 * W) + bload(T(), v, s.o + 73 * W))));
+    OCTOHYDRO_RFENCE();
+    return r;
+  }
+  return bload(T(), v, s.o);
 }
 
 // Kurganov-Tadmor fluxes of the core fields at one face normal to axis d;
@@ -439,7 +480,8 @@ __device__ __forceinline__ void finish_cell(const StepArgs& s, size_t fbase, uin
   } else {
     out = t;
   }
-  st(static_cast<T*>(s.Uout) + fbase, cell, (T)out);
+  // the result is not read again by this kernel: keep it out of the caches
+  __builtin_nontemporal_store((T)out, static_cast<T*>(s.Uout) + fbase + cell);
 }
 
 // Scheduling fence between the per-field PPM evaluations: without it the
@@ -461,13 +503,15 @@ constexpr int ACC_HALF = 4 * ACC_PLANE;
 // no face is complete yet.  Unrolled, so each step does only the work its
 // stencil allows.
 template <typename T, int NF>
-__device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], const T* __restrict__ Uk,
-                                                size_t fs, const Pencil& p, int k0) {
+__device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], Rsrc Uk, uint32_t fs_b,
+                                                const Pencil& p, int k0) {
   T q[5][NF];
 #pragma unroll
-  for (int j = 0; j < 5; ++j)
+  for (int j = 0; j < 5; ++j) {
+    const Src src = pencil_src(p, k0 + j);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) q[j][f] = pencil_value<T>(Uk + f * fs, p, k0 + j);
+    for (int f = 0; f < NF; ++f) q[j][f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+  }
 #pragma unroll
   for (int j = 0; j < 5; ++j)
 #pragma unroll
@@ -514,11 +558,12 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
                                          int lane, bool& bad) {
   const GridArgs& g = s.g;
   const size_t fs = (size_t)g.n_leaves * CELLS;
-  const T* __restrict__ Uk = static_cast<const T*>(s.Uk);
+  const Rsrc Uk = state_rsrc(s.Uk);
+  const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
   const int d = lane >> 5;
   const int a = lane & 7;
   const int zz = (lane >> 3) & 3;
-  const Pencil p = make_pencil(g, li, d, a, 4 * h + zz, fn);
+  const Pencil p = make_pencil<T>(g, li, d, a, 4 * h + zz, fn);
   const int acc_off = d == 0 ? zz * ACC_PLANE + a * ACC_PITCH : zz * ACC_PLANE + a;
   const int acc_step = d == 0 ? 1 : ACC_PITCH;
 
@@ -529,18 +574,22 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
     st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
     Hprev[f] = 0.0;
   }
-  stream_prologue<T, NF>(st, Uk, fs, p, 0);
+  stream_prologue<T, NF>(st, Uk, fs_b, p, 0);
   T qnext[NF];
+  {
+    const Src src = pencil_src(p, 5);
 #pragma unroll
-  for (int f = 0; f < NF; ++f) qnext[f] = pencil_value<T>(Uk + f * fs, p, 5);
+    for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+  }
 #pragma unroll 1
   for (int k = 5; k < TW; ++k) {
     T qn[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) qn[f] = qnext[f];
     if (k + 1 < TW) {
+      const Src src = pencil_src(p, k + 1);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) qnext[f] = pencil_value<T>(Uk + f * fs, p, k + 1);
+      for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
     }
     T H[NF];
     stream_step<T, NF>(ph, d, st, qn, H, bad);
@@ -576,9 +625,10 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
                                         int lane, double dt, double inv_dx, bool& bad) {
   const GridArgs& g = s.g;
   const size_t fs = (size_t)g.n_leaves * CELLS;
-  const T* __restrict__ Uk = static_cast<const T*>(s.Uk);
+  const Rsrc Uk = state_rsrc(s.Uk);
+  const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
   const int x = lane & 7, y = lane >> 3;
-  const Pencil p = make_pencil(g, li, 2, x, y, fn);
+  const Pencil p = make_pencil<T>(g, li, 2, x, y, fn);
   const int k0 = 4 * h;
   const uint32_t leaf_at = (uint32_t)li.leaf * CELLS + y * 8 + x;
 
@@ -589,10 +639,13 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
     st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
     Hprev[f] = 0.0;
   }
-  stream_prologue<T, NF>(st, Uk, fs, p, k0);
+  stream_prologue<T, NF>(st, Uk, fs_b, p, k0);
   T qnext[NF];
+  {
+    const Src src = pencil_src(p, k0 + 5);
 #pragma unroll
-  for (int f = 0; f < NF; ++f) qnext[f] = pencil_value<T>(Uk + f * fs, p, k0 + 5);
+    for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+  }
 #pragma unroll 1
   for (int kk = 5; kk < 10; ++kk) {
     const int k = k0 + kk;
@@ -600,8 +653,9 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
 #pragma unroll
     for (int f = 0; f < NF; ++f) qn[f] = qnext[f];
     if (kk + 1 < 10) {
+      const Src src = pencil_src(p, k + 1);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) qnext[f] = pencil_value<T>(Uk + f * fs, p, k + 1);
+      for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
     }
     T H[NF];
     stream_step<T, NF>(ph, 2, st, qn, H, bad);
@@ -900,6 +954,9 @@ __global__ void k_validate(GridArgs g) {
 static int check_grid(const hydro_grid* gr, const char* fn) {
   if (!gr) return fail(HYDRO_E_ARG, "%s: grid is NULL", fn);
   if (gr->n_leaves <= 0) return fail(HYDRO_E_ARG, "%s: n_leaves must be positive", fn);
+  if (gr->n_leaves > HYDRO_MAX_LEAVES)
+    return fail(HYDRO_E_ARG, "%s: n_leaves %d exceeds %d (one field array must stay below 4 GiB)",
+                fn, gr->n_leaves, HYDRO_MAX_LEAVES);
   if (gr->n_fields < NF_CORE || gr->n_fields > 16)
     return fail(HYDRO_E_ARG, "%s: n_fields must be in [6,16], got %d", fn, gr->n_fields);
   if (gr->dtype != HYDRO_F64 && gr->dtype != HYDRO_F32)
@@ -910,6 +967,11 @@ static int check_grid(const hydro_grid* gr, const char* fn) {
   if (gr->n_nodes > 0 && !gr->children_dev)
     return fail(HYDRO_E_ARG, "%s: children_dev is NULL but n_nodes > 0", fn);
   if (!(gr->gamma > 1.0)) return fail(HYDRO_E_ARG, "%s: gamma must exceed 1", fn);
+  const uint64_t state_bytes = (uint64_t)gr->n_fields * (uint64_t)gr->n_leaves * CELLS *
+                               (gr->dtype == HYDRO_F64 ? 8u : 4u);
+  if (state_bytes > 0xFFFFFFFFull)
+    return fail(HYDRO_E_ARG, "%s: a state array of %llu bytes exceeds 4 GiB", fn,
+                (unsigned long long)state_bytes);
   if (gr->flux_reg_dev && gr->n_slots > 0) {
     if (!gr->face_slot_dev || !gr->fine_slot_dev || !gr->slot_leaf_dev)
       return fail(HYDRO_E_ARG, "%s: flux register set but its tables are not", fn);
