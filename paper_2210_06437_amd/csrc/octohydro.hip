@@ -344,6 +344,9 @@ __device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo&
   return p;
 }
 
+#ifndef OCTOHYDRO_PROLOGUE_BATCH
+#define OCTOHYDRO_PROLOGUE_BATCH 0
+#endif
 #ifndef OCTOHYDRO_FENCE_RESTRICT
 #define OCTOHYDRO_FENCE_RESTRICT 0
 #endif
@@ -465,18 +468,19 @@ __device__ __forceinline__ void core_flux(const Phys<T>& ph, int d, const T (&UL
 }
 
 // Stage combination of one cell: t = Uk + dt L with L = -sum * inv_dx, then
-// t (first stage) or U0 + beta (t - U0).
+// t (first stage) or U0 + beta (t - U0); u0 is the cell's U0 value, loaded
+// by the caller ahead of time.
 template <typename T>
 __device__ __forceinline__ void finish_cell(const StepArgs& s, size_t fbase, uint32_t cell, T uk,
-                                            double sum, bool has_src, double src, double dt,
-                                            double inv_dx) {
+                                            T u0, double sum, bool has_src, double src,
+                                            double dt, double inv_dx) {
   double lrate = -sum * inv_dx;
   if (has_src) lrate = lrate + src;
   const double t = (double)uk + dt * lrate;
   double out;
   if (s.U0) {
-    const double u0 = (double)ld(static_cast<const T*>(s.U0) + fbase, cell);
-    out = u0 + s.beta * (t - u0);
+    const double u = (double)u0;
+    out = u + s.beta * (t - u);
   } else {
     out = t;
   }
@@ -505,6 +509,7 @@ constexpr int ACC_HALF = 4 * ACC_PLANE;
 template <typename T, int NF>
 __device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], Rsrc Uk, uint32_t fs_b,
                                                 const Pencil& p, int k0) {
+#if OCTOHYDRO_PROLOGUE_BATCH
   T q[5][NF];
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
@@ -519,6 +524,29 @@ __device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], Rsrc Uk, uint3
       T ul, ur;
       ppm_push(st[f], q[j][f], j, ul, ur);
     }
+#else
+  // one position in flight ahead of the recurrences
+  T cur[NF], nxt[NF];
+  {
+    const Src src = pencil_src(p, k0);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) cur[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+  }
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    if (j + 1 < 5) {
+      const Src src = pencil_src(p, k0 + j + 1);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) nxt[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      T ul, ur;
+      ppm_push(st[f], cur[f], j, ul, ur);
+      cur[f] = nxt[f];
+    }
+  }
+#endif
 }
 
 // A steady stream step: feed the next value of every field and evaluate the
@@ -627,6 +655,7 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
   const size_t fs = (size_t)g.n_leaves * CELLS;
   const Rsrc Uk = state_rsrc(s.Uk);
   const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
+  const Rsrc U0 = state_rsrc(s.U0 ? s.U0 : s.Uk);
   const int x = lane & 7, y = lane >> 3;
   const Pencil p = make_pencil<T>(g, li, 2, x, y, fn);
   const int k0 = 4 * h;
@@ -657,6 +686,16 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
 #pragma unroll
       for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
     }
+    // U0 of the cell this step finishes: issued now, consumed after the
+    // face evaluation, so the load's latency is covered by it
+    T u0v[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) u0v[f] = T(0);
+    if (s.U0 && kk >= 6) {
+      const uint32_t cell_b = (uint32_t)sizeof(T) * (leaf_at + (k - 6) * 64);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) u0v[f] = bload(T(), FieldView{U0, f * fs_b}, cell_b);
+    }
     T H[NF];
     stream_step<T, NF>(ph, 2, st, qn, H, bad);
     if (g.reg && (k == 5 || k == TW - 1)) record_face<T, NF>(g, fn, k - 5, x, y, H);
@@ -679,7 +718,7 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         const double sum = acc[f * ACC_HALF + ai] + ((double)H[f] - Hprev[f]);
-        finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, st[f].qy, sum,
+        finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, st[f].qy, u0v[f], sum,
                        rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
       }
     }
