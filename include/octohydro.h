@@ -133,6 +133,14 @@ typedef struct hydro_grid {
    *   s_z: 0
    *   E:   omega^2 (s_x (x - 0.5) + s_y (y - 0.5))                          */
   double omega;
+  /* Restricted copies of the refined blocks: caller-owned device scratch of
+   * n_fields * n_nodes * 512 elements of `dtype`, laid out
+   * [n_fields][n_nodes][8][8][8]; required when n_nodes > 0, ignored
+   * otherwise.  Every substep first writes the coarse (8-cell mean) copy of
+   * each refined node of its input state here, then reads the ghost cells
+   * of refined face neighbours from it.  Two calls that run at the same
+   * time need two buffers. */
+  void* node_state_dev;
 } hydro_grid;
 
 /*

@@ -27,6 +27,7 @@ HYDRO_OK, HYDRO_E_ARG, HYDRO_E_TABLE, HYDRO_E_UNPHYSICAL, HYDRO_E_HIP, HYDRO_E_U
 HYDRO_F64, HYDRO_F32 = 0, 1
 HYDRO_SAME_LEAF, HYDRO_SAME_REFINED, HYDRO_COARSER_LEAF = 0, 1, 2
 HYDRO_FLAG_VALIDATE = 1
+HYDRO_MAX_LEAVES = 1048575
 HYDRO_STATUS_UNPHYSICAL, HYDRO_STATUS_TABLE = 1, 2
 
 EXPORTS = [
@@ -66,6 +67,7 @@ class hydro_grid(ctypes.Structure):
         ("slot_leaf_dev", ctypes.c_void_p),
         ("flux_reg_dev", ctypes.c_void_p),
         ("omega", ctypes.c_double),
+        ("node_state_dev", ctypes.c_void_p),
     ]
 
 
@@ -224,6 +226,11 @@ class Grid:
             nbr_dev=self.nbr.data_ptr(), nbr_kind_dev=self.kind.data_ptr(),
             children_dev=self.children.data_ptr(), status_dev=self.status.data_ptr(),
             gamma=float(gamma), dual_energy_eta1=float(eta1), omega=float(omega))
+        # scratch for the restricted copies of the refined blocks
+        if len(kids):
+            self.node_state = torch.empty((self.n_fields, len(kids), 8, 8, 8),
+                                          dtype=self.torch_dtype, device=dev)
+            self.c.node_state_dev = self.node_state.data_ptr()
         self.reflux = bool(reflux)
         if self.reflux:
             fs, fi, sl, ob = hydro_build_reflux(coord, nbr, kind)

@@ -44,6 +44,10 @@ constexpr int NF_CORE = 6;  // rho, sx, sy, sz, E, tau
 constexpr int ACC_PITCH = 9;  // LDS row pitch (doubles) of the accumulator
 constexpr int ACC_PLANE = SUB * ACC_PITCH;
 constexpr int ACC_FIELD = SUB * ACC_PLANE;
+// A buffer offset past the end of every array the kernels address (array
+// sizes are bounded below it on the host): a buffer load there returns 0
+// without touching memory.
+constexpr uint32_t OFF_NONE = 0xFFFFF000u;
 
 struct GridArgs {
   int32_t n_leaves;
@@ -63,6 +67,7 @@ struct GridArgs {
   const int32_t* slot_leaf;
   double* reg;
   double omega;  // rotating-frame angular velocity (0: no sources)
+  void* rstate;  // restricted copies of the refined nodes [nf][n_nodes][512]
 };
 
 // Values per register slot and field: 64 coarse face fluxes, then the 16x16
@@ -143,6 +148,43 @@ __global__ void __launch_bounds__(256)
     }
     G[idx] = v;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Restricted copies of the refined nodes (the coarse side of a coarse-fine
+// face, Sec. VI): coarse cell (x, y, z) of node n is the mean of the 8 cells
+// of child (x>>2, y>>2, z>>2) that cover it, summed in the same fixed order as
+// the ghost fill.  Cells of a missing child are never read; they are set to 0.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  typedef double2 type;
+};
+template <>
+struct Pair<float> {
+  typedef float2 type;
+};
+
+// Workgroup (node, field) of 512 threads, thread = coarse cell; the two x
+// neighbours of each fine pair are read as one aligned 2-element load.
+template <typename T>
+__global__ void __launch_bounds__(512)
+    k_restrict(GridArgs g, const T* __restrict__ U, T* __restrict__ R) {
+  typedef typename Pair<T>::type P;
+  const int node = blockIdx.x, f = blockIdx.y, c = threadIdx.x;
+  const int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+  const int child = g.children[8 * node + (z >> 2) * 4 + (y >> 2) * 2 + (x >> 2)];
+  T v = T(0);
+  if (child >= 0) {
+    const T* u = U + (size_t)f * g.n_leaves * CELLS + (size_t)child * CELLS +
+                 ((2 * z) & 7) * 64 + ((2 * y) & 7) * 8 + ((2 * x) & 7);
+    const P a = *reinterpret_cast<const P*>(u), b = *reinterpret_cast<const P*>(u + 8),
+            d = *reinterpret_cast<const P*>(u + 64), e = *reinterpret_cast<const P*>(u + 72);
+    v = T(0.125) * (((a.x + a.y) + (b.x + b.y)) + ((d.x + d.y) + (e.x + e.y)));
+  }
+  R[((size_t)f * g.n_nodes + node) * CELLS + c] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -296,11 +338,10 @@ __device__ __forceinline__ void record_face(const GridArgs& g, const FaceNbr& fn
 // A lane's pencil along axis d through transverse cell (a, b): where each of
 // its 14 stream values comes from, as byte offsets into a field array.
 // Interior value k sits at off + (k-3) sd; each ghost value k in
-// {0,1,2,11,12,13} comes from gofs[] -- a same-level cell, the covering
-// coarse cell (injection), or, on a refined side, the first of the 8 fine
-// cells it averages, which lie at +{0,1,8,9,64,65,72,73} elements.  The
-// sources are the same for every field, so they are worked out once per
-// pencil.
+// {0,1,2,11,12,13} comes from gofs[] -- a same-level cell or the covering
+// coarse cell (injection) of the state, or, on a refined side (ref_lo /
+// ref_hi), a cell of the refined node's restricted copy.  The sources are the
+// same for every field, so they are worked out once per pencil.
 typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
 
 struct Pencil {
@@ -320,8 +361,8 @@ __device__ __forceinline__ uint32_t ghost_offset(const GridArgs& g, const LeafIn
     return id * CELLS + (4 * (bz & 1) + (lz >> 1)) * 64 + (4 * (by & 1) + (ly >> 1)) * 8 +
            (4 * (bx & 1) + (lx >> 1));
   }
-  const int child = g.children[8 * id + (lz >> 2) * 4 + (ly >> 2) * 2 + (lx >> 2)];
-  return child * CELLS + ((2 * lz) & 7) * 64 + ((2 * ly) & 7) * 8 + ((2 * lx) & 7);
+  // refined neighbour: the coarse cell of the node's restricted copy
+  return id * CELLS + lz * 64 + ly * 8 + lx;
 }
 
 template <typename T>
@@ -352,6 +393,14 @@ __device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo&
 // the U0 loads) instead of carrying it through the recurrence.
 #ifndef OCTOHYDRO_Z_RELOAD
 #define OCTOHYDRO_Z_RELOAD 0
+#endif
+// Z phase: read the accumulator of the cell a step finishes at the top of
+// the step; load U0 of a step's cell one step ahead.
+#ifndef OCTOHYDRO_ACC_EARLY
+#define OCTOHYDRO_ACC_EARLY 0
+#endif
+#ifndef OCTOHYDRO_U0_AHEAD
+#define OCTOHYDRO_U0_AHEAD 0
 #endif
 #ifndef OCTOHYDRO_PROLOGUE_BATCH
 #define OCTOHYDRO_PROLOGUE_BATCH 0
@@ -385,20 +434,27 @@ __device__ __forceinline__ void st(T* __restrict__ base, uint32_t off, T v) {
 // index known only at run time the ghost offset is picked by a select chain
 // over the six values.
 struct Src {
-  uint32_t o;
-  bool ref;
+  uint32_t o;    // offset of the value in its array
+  uint32_t ouk;  // offset into the stage input, OFF_NONE on a refined side
+  uint32_t orn;  // offset into the node copies, OFF_NONE elsewhere
+  bool ref;      // this lane's value comes from a node copy
+  bool any_ref;  // some lane of the wave reads a node copy (wave-uniform)
 };
 
 __device__ __forceinline__ Src pencil_src(const Pencil& p, int k) {
   Src s;
   if (k >= GH && k < GH + SUB) {
-    s.o = p.off + (uint32_t)(k - GH) * p.sd;
-    s.ref = false;
+    s.o = s.ouk = p.off + (uint32_t)(k - GH) * p.sd;
+    s.orn = OFF_NONE;
+    s.ref = s.any_ref = false;
     return s;
   }
   s.o = k == 0 ? p.gofs[0] : k == 1 ? p.gofs[1] : k == 2 ? p.gofs[2]
       : k == 11 ? p.gofs[3] : k == 12 ? p.gofs[4] : p.gofs[5];
   s.ref = k < GH ? p.ref_lo : p.ref_hi;
+  s.any_ref = __any(s.ref);
+  s.ouk = s.ref ? OFF_NONE : s.o;
+  s.orn = s.ref ? s.o : OFF_NONE;
   return s;
 }
 
@@ -410,9 +466,10 @@ __device__ __forceinline__ Src pencil_src(const Pencil& p, int k) {
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 constexpr int RSRC_WORD3 = 0x00020000;  // raw dword data format (gfx9 family)
 
-__device__ __forceinline__ Rsrc state_rsrc(const void* base) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, -1, RSRC_WORD3);
+__device__ __forceinline__ Rsrc state_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, RSRC_WORD3);
 }
+
 
 // Field view: the array's resource and the field's scalar byte offset.
 struct FieldView {
@@ -427,20 +484,26 @@ __device__ __forceinline__ float bload(float, const FieldView& v, uint32_t o) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v.r, (int)o, (int)v.fo, 0));
 }
 
-// The value a stream position takes in one field.
+// The two arrays stream values come from: the stage input (all interior and
+// same-level or coarser ghosts) and the restricted node copies (ghosts on a
+// refined side), each with its field stride in bytes.
+struct Sources {
+  Rsrc uk, rn;
+  uint32_t uk_fs, rn_fs;
+};
+
+// The value a stream position takes in field f.  Where some lane of the
+// wave reads a node copy, every lane loads from both arrays, one load with
+// an offset past the end (which reads 0 without a memory access), and keeps
+// its own: no divergent branch.
 template <typename T>
-__device__ __forceinline__ T src_value(const FieldView& v, Src s) {
-  constexpr uint32_t W = sizeof(T);
-  if (s.ref) {
-    OCTOHYDRO_RFENCE();
-    const T r = T(0.125) * (((bload(T(), v, s.o) + bload(T(), v, s.o + W)) +
-                             (bload(T(), v, s.o + 8 * W) + bload(T(), v, s.o + 9 * W))) +
-                            ((bload(T(), v, s.o + 64 * W) + bload(T(), v, s.o + 65 * W)) +
-                             (bload(T(), v, s.o + 72 * W) + bload(T(), v, s.o + 73 * W))));
-    OCTOHYDRO_RFENCE();
-    return r;
+__device__ __forceinline__ T src_value(const Sources& S, int f, Src s) {
+  if (s.any_ref) {
+    const T a = bload(T(), FieldView{S.uk, f * S.uk_fs}, s.ouk);
+    const T b = bload(T(), FieldView{S.rn, f * S.rn_fs}, s.orn);
+    return s.ref ? b : a;
   }
-  return bload(T(), v, s.o);
+  return bload(T(), FieldView{S.uk, f * S.uk_fs}, s.o);
 }
 
 // Kurganov-Tadmor fluxes of the core fields at one face normal to axis d;
@@ -517,7 +580,7 @@ constexpr int ACC_HALF = 4 * ACC_PLANE;
 // no face is complete yet.  Unrolled, so each step does only the work its
 // stencil allows.
 template <typename T, int NF>
-__device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], Rsrc Uk, uint32_t fs_b,
+__device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], const Sources& S,
                                                 const Pencil& p, int k0) {
 #if OCTOHYDRO_PROLOGUE_BATCH
   T q[5][NF];
@@ -525,7 +588,7 @@ __device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], Rsrc Uk, uint3
   for (int j = 0; j < 5; ++j) {
     const Src src = pencil_src(p, k0 + j);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) q[j][f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+    for (int f = 0; f < NF; ++f) q[j][f] = src_value<T>(S, f, src);
   }
 #pragma unroll
   for (int j = 0; j < 5; ++j)
@@ -540,14 +603,14 @@ __device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], Rsrc Uk, uint3
   {
     const Src src = pencil_src(p, k0);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) cur[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+    for (int f = 0; f < NF; ++f) cur[f] = src_value<T>(S, f, src);
   }
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
     if (j + 1 < 5) {
       const Src src = pencil_src(p, k0 + j + 1);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) nxt[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+      for (int f = 0; f < NF; ++f) nxt[f] = src_value<T>(S, f, src);
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -597,8 +660,10 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
                                          int lane, bool& bad) {
   const GridArgs& g = s.g;
   const size_t fs = (size_t)g.n_leaves * CELLS;
-  const Rsrc Uk = state_rsrc(s.Uk);
+  const Rsrc Uk = state_rsrc(s.Uk, (uint32_t)(g.nf * fs * sizeof(T)));
   const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
+  const uint32_t rn_fs = (uint32_t)((size_t)g.n_nodes * CELLS * sizeof(T));
+  const Sources S{Uk, state_rsrc(g.rstate, g.rstate ? (uint32_t)g.nf * rn_fs : 0u), fs_b, rn_fs};
   const int d = lane >> 5;
   const int a = lane & 7;
   const int zz = (lane >> 3) & 3;
@@ -613,12 +678,12 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
     st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
     Hprev[f] = 0.0;
   }
-  stream_prologue<T, NF>(st, Uk, fs_b, p, 0);
+  stream_prologue<T, NF>(st, S, p, 0);
   T qnext[NF];
   {
     const Src src = pencil_src(p, 5);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+    for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(S, f, src);
   }
 #pragma unroll 1
   for (int k = 5; k < TW; ++k) {
@@ -628,7 +693,7 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
     if (k + 1 < TW) {
       const Src src = pencil_src(p, k + 1);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+      for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(S, f, src);
     }
     T H[NF];
     stream_step<T, NF>(ph, d, st, qn, H, bad);
@@ -664,9 +729,11 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
                                         int lane, double dt, double inv_dx, bool& bad) {
   const GridArgs& g = s.g;
   const size_t fs = (size_t)g.n_leaves * CELLS;
-  const Rsrc Uk = state_rsrc(s.Uk);
+  const Rsrc Uk = state_rsrc(s.Uk, (uint32_t)(g.nf * fs * sizeof(T)));
   const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
-  const Rsrc U0 = state_rsrc(s.U0 ? s.U0 : s.Uk);
+  const uint32_t rn_fs = (uint32_t)((size_t)g.n_nodes * CELLS * sizeof(T));
+  const Sources S{Uk, state_rsrc(g.rstate, g.rstate ? (uint32_t)g.nf * rn_fs : 0u), fs_b, rn_fs};
+  const Rsrc U0 = state_rsrc(s.U0 ? s.U0 : s.Uk, (uint32_t)(g.nf * fs * sizeof(T)));
   const int x = lane & 7, y = lane >> 3;
   const Pencil p = make_pencil<T>(g, li, 2, x, y, fn);
   const int k0 = 4 * h;
@@ -679,13 +746,18 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
     st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
     Hprev[f] = 0.0;
   }
-  stream_prologue<T, NF>(st, Uk, fs_b, p, k0);
+  stream_prologue<T, NF>(st, S, p, k0);
   T qnext[NF];
   {
     const Src src = pencil_src(p, k0 + 5);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+    for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(S, f, src);
   }
+#if OCTOHYDRO_U0_AHEAD
+  T u0next[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) u0next[f] = T(0);
+#endif
 #pragma unroll 1
   for (int kk = 5; kk < 10; ++kk) {
     const int k = k0 + kk;
@@ -695,22 +767,43 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
     if (kk + 1 < 10) {
       const Src src = pencil_src(p, k + 1);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(FieldView{Uk, f * fs_b}, src);
+      for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(S, f, src);
     }
     // U0 of the cell this step finishes: issued now, consumed after the
     // face evaluation, so the load's latency is covered by it
     T u0v[NF], ukv[NF];
+    double accv[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) u0v[f] = ukv[f] = T(0);
+    for (int f = 0; f < NF; ++f) {
+      u0v[f] = ukv[f] = T(0);
+      accv[f] = 0.0;
+    }
+#if OCTOHYDRO_U0_AHEAD
+    // U0 of this step's cell was loaded one step earlier
+#pragma unroll
+    for (int f = 0; f < NF; ++f) u0v[f] = u0next[f];
+    if (s.U0 && kk + 1 >= 6 && kk + 1 < 10) {
+      const uint32_t nb_b = (uint32_t)sizeof(T) * (leaf_at + (k + 1 - 6) * 64);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) u0next[f] = bload(T(), FieldView{U0, f * fs_b}, nb_b);
+    }
+#endif
     if (kk >= 6) {
       const uint32_t cell_b = (uint32_t)sizeof(T) * (leaf_at + (k - 6) * 64);
+#if !OCTOHYDRO_U0_AHEAD
       if (s.U0) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) u0v[f] = bload(T(), FieldView{U0, f * fs_b}, cell_b);
       }
+#endif
 #if OCTOHYDRO_Z_RELOAD
 #pragma unroll
       for (int f = 0; f < NF; ++f) ukv[f] = bload(T(), FieldView{Uk, f * fs_b}, cell_b);
+#endif
+#if OCTOHYDRO_ACC_EARLY
+      const int ai0 = (k - 6 - k0) * ACC_PLANE + y * ACC_PITCH + x;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) accv[f] = acc[f * ACC_HALF + ai0];
 #endif
     }
     T H[NF];
@@ -738,7 +831,11 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
       }
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
+#if OCTOHYDRO_ACC_EARLY
+        const double sum = accv[f] + ((double)H[f] - Hprev[f]);
+#else
         const double sum = acc[f * ACC_HALF + ai] + ((double)H[f] - Hprev[f]);
+#endif
 #if OCTOHYDRO_Z_RELOAD
         const T uk = ukv[f];
 #else
@@ -1034,8 +1131,8 @@ static int check_grid(const hydro_grid* gr, const char* fn) {
   if (!(gr->gamma > 1.0)) return fail(HYDRO_E_ARG, "%s: gamma must exceed 1", fn);
   const uint64_t state_bytes = (uint64_t)gr->n_fields * (uint64_t)gr->n_leaves * CELLS *
                                (gr->dtype == HYDRO_F64 ? 8u : 4u);
-  if (state_bytes > 0xFFFFFFFFull)
-    return fail(HYDRO_E_ARG, "%s: a state array of %llu bytes exceeds 4 GiB", fn,
+  if (state_bytes > OFF_NONE)
+    return fail(HYDRO_E_ARG, "%s: a state array of %llu bytes exceeds 4 GiB - 4 KiB", fn,
                 (unsigned long long)state_bytes);
   if (gr->flux_reg_dev && gr->n_slots > 0) {
     if (!gr->face_slot_dev || !gr->fine_slot_dev || !gr->slot_leaf_dev)
@@ -1068,6 +1165,7 @@ static GridArgs grid_args(const hydro_grid* gr) {
   g.slot_leaf = reflux ? gr->slot_leaf_dev : nullptr;
   g.reg = reflux ? gr->flux_reg_dev : nullptr;
   g.omega = gr->omega;
+  g.rstate = gr->n_nodes > 0 ? gr->node_state_dev : nullptr;
   return g;
 }
 
@@ -1095,6 +1193,22 @@ static int grid_blocks(int64_t work, int threads, int cap) {
   int64_t b = (work + threads - 1) / threads;
   if (b > cap) b = cap;
   return (int)(b < 1 ? 1 : b);
+}
+
+// The restricted node copies of a substep's input state (nothing without
+// refined nodes).
+static int restrict_launch(const hydro_grid* gr, const void* Uk, hipStream_t st) {
+  if (gr->n_nodes <= 0) return HYDRO_OK;
+  const GridArgs g = grid_args(gr);
+  const dim3 grid(g.n_nodes, g.nf);
+  if (gr->dtype == HYDRO_F64)
+    hipLaunchKernelGGL(k_restrict<double>, grid, dim3(CELLS), 0, st, g,
+                       static_cast<const double*>(Uk), static_cast<double*>(gr->node_state_dev));
+  else
+    hipLaunchKernelGGL(k_restrict<float>, grid, dim3(CELLS), 0, st, g,
+                       static_cast<const float*>(Uk), static_cast<float*>(gr->node_state_dev));
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
 }
 
 // Launch options per (dtype, n_fields), set by hydro_set_option (the
@@ -1168,6 +1282,15 @@ static int step_common(const hydro_grid* gr, const void* U0, const void* Uk, voi
   if (Uout == Uk || (U0 && Uout == U0))
     return fail(HYDRO_E_ARG, "%s: Uout may not alias an input", fn);
   if (flags & ~HYDRO_FLAG_VALIDATE) return fail(HYDRO_E_ARG, "%s: unknown flags", fn);
+  if (gr->n_nodes > 0) {
+    if (!gr->node_state_dev)
+      return fail(HYDRO_E_ARG, "%s: node_state_dev is NULL but n_nodes > 0", fn);
+    const uint64_t node_bytes = (uint64_t)gr->n_fields * (uint64_t)gr->n_nodes * CELLS *
+                                (gr->dtype == HYDRO_F64 ? 8u : 4u);
+    if (node_bytes > OFF_NONE)
+      return fail(HYDRO_E_ARG, "%s: node_state of %llu bytes exceeds 4 GiB - 4 KiB", fn,
+                  (unsigned long long)node_bytes);
+  }
   a.g = grid_args(gr);
   a.U0 = U0;
   a.Uk = Uk;
@@ -1204,24 +1327,28 @@ static int rk3_launch(const hydro_grid* gr, const void* Un, void* W1, void* W2, 
     return fail(HYDRO_E_ARG, "hydro_rk3_step: null buffer");
   if (Unext == Un || Unext == W2 || W1 == W2 || W1 == Un || W2 == Un)
     return fail(HYDRO_E_ARG, "hydro_rk3_step: buffers alias");
+  // every argument is checked before anything is queued
+  StepArgs a;
+  rc = step_common(gr, nullptr, Un, W1, dt, 1.0, 0, "hydro_rk3_step", a);
+  if (rc) return rc;
   if (cfl > 0.0) {
     rc = cfl_launch(gr, Un, cfl, dt, st);
     if (rc) return rc;
   }
-  StepArgs a;
-  rc = step_common(gr, nullptr, Un, W1, dt, 1.0, 0, "hydro_rk3_step", a);
-  if (rc) return rc;
+  if ((rc = restrict_launch(gr, Un, st))) return rc;
   HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
   if ((rc = reflux_launch(gr, a, st))) return rc;
   a.U0 = Un;
   a.Uk = W1;
   a.Uout = W2;
   a.beta = 0.25;
+  if ((rc = restrict_launch(gr, W1, st))) return rc;
   HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
   if ((rc = reflux_launch(gr, a, st))) return rc;
   a.Uk = W2;
   a.Uout = Unext;
   a.beta = 2.0 / 3.0;
+  if ((rc = restrict_launch(gr, W2, st))) return rc;
   HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
   if ((rc = reflux_launch(gr, a, st))) return rc;
   return HYDRO_OK;
@@ -1341,6 +1468,7 @@ int hydro_step(const hydro_grid* gr, const void* U0, const void* Uk, void* Uout,
     rc = validate_table(gr, st);
     if (rc) return rc;
   }
+  if ((rc = restrict_launch(gr, Uk, st))) return rc;
   HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
   return reflux_launch(gr, a, st);
 }
@@ -1372,6 +1500,7 @@ int hydro_step_per_leaf(const hydro_grid* gr, const void* U0, const void* Uk, vo
     HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     g_pool.events.push_back(e);
   }
+  if ((rc = restrict_launch(gr, Uk, st))) return rc;
   // pool streams start after the work already queued on `stream`
   HIP_TRY(hipEventRecord(g_pool.events[0], st));
   for (int i = 0; i < n_streams; ++i) HIP_TRY(hipStreamWaitEvent(g_pool.streams[i], g_pool.events[0], 0));

@@ -190,3 +190,25 @@ def test_flux_register_tables_are_consistent(hb, which):
     assert sorted(cover) == list(range(len(sl)))
     for s, qs in cover.items():
         assert sorted(qs) == [0, 1, 2, 3], (s, qs)
+
+
+def test_step_requires_node_scratch_when_the_tree_has_refined_nodes(hb):
+    lib = hb._lib
+    g = _raw_grid(hb, n_nodes=3, children_dev=16)
+    a, b = ctypes.c_void_p(64), ctypes.c_void_p(128)
+    assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
+    assert "node_state_dev" in hb.hydro_last_error()
+    assert lib.hydro_rk3_step(ctypes.byref(g), a, b, ctypes.c_void_p(192), ctypes.c_void_p(256),
+                              0.4, a, None) == hb.HYDRO_E_ARG
+    assert "node_state_dev" in hb.hydro_last_error()
+
+
+def test_grid_size_limits_are_checked_on_the_host(hb):
+    lib = hb._lib
+    a, b = ctypes.c_void_p(64), ctypes.c_void_p(128)
+    g = _raw_grid(hb, n_leaves=hb.HYDRO_MAX_LEAVES + 1)
+    assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
+    # 16 binary64 fields of 65536 leaves are 4 GiB: one state array too many
+    g = _raw_grid(hb, n_leaves=65536, n_fields=16)
+    assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
+    assert "4 GiB" in hb.hydro_last_error()
