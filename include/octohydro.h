@@ -72,6 +72,8 @@ extern "C" {
 
 /* flags */
 #define HYDRO_FLAG_VALIDATE 1u  /* check table ids on the device and wait    */
+#define HYDRO_FLAG_NODES_READY 2u /* node_state_dev already holds the restricted
+                                     copies of this call's Uk: skip them      */
 
 /*
  * A batch of leaves (Sec. IV-C): host struct, device arrays.
@@ -193,7 +195,12 @@ int hydro_fill_ghosts(const hydro_grid* grid, const void* U_dev, void* G_dev, vo
  * face gets q = (Havg - Hc)/dx with Havg = 0.25((H00 + H10) + (H01 + H11))
  * of the 4 fine fluxes and Hc its own, and Uout -= w dt q on its high face,
  * += on its low face (w = 1 without U0, else beta; faces x, y, z, low first).
- * Uout_dev may alias neither Uk_dev nor U0_dev.  flags: HYDRO_FLAG_VALIDATE.
+ * Before the fluxes, the restricted copies of the refined nodes are made
+ * from Uk into grid->node_state_dev (when the tree has refined nodes).
+ * Uout_dev may alias neither Uk_dev nor U0_dev.  flags: HYDRO_FLAG_VALIDATE;
+ * HYDRO_FLAG_NODES_READY when the node copies were made from this Uk by an
+ * earlier call and not overwritten since (the caller's promise: it is not
+ * checked).
  */
 int hydro_step(const hydro_grid* grid, const void* U0_dev, const void* Uk_dev, void* Uout_dev,
                const double* dt_dev, double beta, uint32_t flags, void* stream);

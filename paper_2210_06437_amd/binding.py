@@ -27,6 +27,7 @@ HYDRO_OK, HYDRO_E_ARG, HYDRO_E_TABLE, HYDRO_E_UNPHYSICAL, HYDRO_E_HIP, HYDRO_E_U
 HYDRO_F64, HYDRO_F32 = 0, 1
 HYDRO_SAME_LEAF, HYDRO_SAME_REFINED, HYDRO_COARSER_LEAF = 0, 1, 2
 HYDRO_FLAG_VALIDATE = 1
+HYDRO_FLAG_NODES_READY = 2
 HYDRO_MAX_LEAVES = 1048575
 HYDRO_STATUS_UNPHYSICAL, HYDRO_STATUS_TABLE = 1, 2
 

@@ -1281,7 +1281,8 @@ static int step_common(const hydro_grid* gr, const void* U0, const void* Uk, voi
   if (!Uk || !Uout || !dt) return fail(HYDRO_E_ARG, "%s: Uk, Uout and dt must be set", fn);
   if (Uout == Uk || (U0 && Uout == U0))
     return fail(HYDRO_E_ARG, "%s: Uout may not alias an input", fn);
-  if (flags & ~HYDRO_FLAG_VALIDATE) return fail(HYDRO_E_ARG, "%s: unknown flags", fn);
+  if (flags & ~(HYDRO_FLAG_VALIDATE | HYDRO_FLAG_NODES_READY))
+    return fail(HYDRO_E_ARG, "%s: unknown flags", fn);
   if (gr->n_nodes > 0) {
     if (!gr->node_state_dev)
       return fail(HYDRO_E_ARG, "%s: node_state_dev is NULL but n_nodes > 0", fn);
@@ -1468,7 +1469,7 @@ int hydro_step(const hydro_grid* gr, const void* U0, const void* Uk, void* Uout,
     rc = validate_table(gr, st);
     if (rc) return rc;
   }
-  if ((rc = restrict_launch(gr, Uk, st))) return rc;
+  if (!(flags & HYDRO_FLAG_NODES_READY) && (rc = restrict_launch(gr, Uk, st))) return rc;
   HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
   return reflux_launch(gr, a, st);
 }

@@ -449,3 +449,22 @@ def test_rotating_frame_sources_match_oracle(env, reflux):
     assert np.all(err <= TOL64), err
     inert, _, _ = oracle.rk3_step(T, w.U, 0.4, reflux=reflux)
     assert not np.array_equal(ref, inert)  # the sources act
+
+
+def test_reused_node_copies_give_the_same_step(env):
+    # a second substep on the same input with HYDRO_FLAG_NODES_READY reuses
+    # the restricted node copies of the first one: identical bits, and it
+    # matches the oracle
+    torch, hb = env
+    w = inputs.blobs(base=4, max_level=3)
+    print(f"case amr-base4-levels0-3-nf11 nodes-ready: {w.n_leaves} leaves", flush=True)
+    grid, T, U = _setup(env, w)
+    assert grid.c.n_nodes > 0
+    dt = torch.tensor([0.2 * oracle.cfl_dt(T, w.U, 0.4)], dtype=torch.float64, device="cuda")
+    a, b = grid.empty_state(), grid.empty_state()
+    hb.hydro_step(grid, None, U, a, dt, 1.0)
+    hb.hydro_step(grid, None, U, b, dt, 1.0, flags=hb.HYDRO_FLAG_NODES_READY)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    ref, _ = oracle.step(T, w.U, dt.item())
+    assert np.all(_rel(a.cpu().numpy(), ref) <= TOL64)
