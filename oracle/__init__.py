@@ -54,6 +54,7 @@ class _OGrid(ctypes.Structure):
         ("gamma", ctypes.c_double),
         ("eta1", ctypes.c_double),
         ("omega", ctypes.c_double),
+        ("recon", ctypes.c_int32),
     ]
 
 
@@ -96,6 +97,10 @@ def _load():
     lib.oracle_rk3_step_reflux.argtypes = [ctypes.POINTER(_OGrid), vp, vp, vp, f64, f64,
                                            ctypes.POINTER(f64), ctypes.c_int]
     lib.oracle_rk3_step_reflux.restype = ctypes.c_int64
+    lib.oracle_point_value.argtypes = [vp, vp, vp]
+    lib.oracle_point_value.restype = f64
+    lib.oracle_face_flux_3d.argtypes = [ctypes.POINTER(_OGrid), vp, ctypes.c_int, vp, vp]
+    lib.oracle_face_flux_3d.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -152,9 +157,23 @@ def set_omega(omega: float) -> None:
     _OMEGA[0] = float(omega)
 
 
+# Reconstruction used by every call: 0 = PPM per axis with the flux at the
+# face centre, 1 = full 3D reconstruction with the 9-point Simpson flux per
+# face (Sec. V-B-1).  Set with set_recon().
+_RECON = [0]
+RECON_AXIS, RECON_3D = 0, 1
+
+
+def set_recon(mode: int) -> None:
+    if mode not in (RECON_AXIS, RECON_3D):
+        raise ValueError(f"unknown reconstruction {mode}")
+    _RECON[0] = int(mode)
+
+
 def _grid(table: Table, nf: int, gamma: float, eta1: float) -> _OGrid:
     g = _OGrid()
     g.omega = _OMEGA[0]
+    g.recon = _RECON[0]
     g.n_leaves = table.n_leaves
     g.nf = nf
     g.base = table.base
@@ -188,6 +207,29 @@ def ppm_1d(q):
     qR = np.full(n, np.nan)
     _load().oracle_ppm_1d(_ptr(q), n, _ptr(qL), _ptr(qR))
     return qL, qR
+
+
+def point_value(tile, t, p):
+    """3D reconstruction: value of a 14^3 tile (one field) at the point
+    t + p/2 of tile cell t, p in {-1,0,1}^3 without 0."""
+    tile = _c64(tile)
+    lib = _load()
+    tt = np.ascontiguousarray(t, np.int32)
+    pp = np.ascontiguousarray(p, np.int32)
+    return lib.oracle_point_value(_ptr(tile), _ptr(tt), _ptr(pp))
+
+
+def face_flux_3d(tiles, d, tl, gamma=GAMMA, eta1=ETA1):
+    """9-point Simpson flux (3D reconstruction) of the face normal to d
+    between tile cells tl and tl + d of tiles[nf][14][14][14]; (H, n_bad)."""
+    tiles = _c64(tiles)
+    nf = tiles.shape[0]
+    H = np.empty(nf, np.float64)
+    tt = np.ascontiguousarray(tl, np.int32)
+    tab = Table(np.zeros((1, 4), np.int32), 1)
+    bad = _load().oracle_face_flux_3d(ctypes.byref(_grid(tab, nf, gamma, eta1)), _ptr(tiles),
+                                      int(d), _ptr(tt), _ptr(H))
+    return H, bad
 
 
 def face_flux(d, UL, UR, gamma=GAMMA, eta1=ETA1):

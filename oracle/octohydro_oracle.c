@@ -384,6 +384,73 @@ static double rotating_source(const ogrid* g, const double* Uk, int32_t n, int32
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Full three-dimensional reconstruction and face quadrature (Sec. V-B-1:    */
+/* the reconstruct kernel does a full 3D reconstruction, the flux kernel     */
+/* integrates the face fluxes by quadrature).                                */
+/* ------------------------------------------------------------------------ */
+
+/* Value of one field (tile Tf) of tile cell t at the point t + p/2, p in
+ * {-1,0,1}^3 \ {0}: a face centre, edge midpoint or corner of the cell.  It
+ * comes from the same PPM as along an axis, applied to the line of cells
+ * t + m e, m = -2..2, where e is p or -p, whichever has its first non-zero
+ * component positive (13 lines through each cell).  The point is the right
+ * end (+e/2) of the cell's monotonised parabola when e = p, the left end
+ * otherwise. */
+double oracle_point_value(const double* Tf, const int32_t t[3], const int32_t p[3]) {
+  const int32_t first = p[0] != 0 ? p[0] : (p[1] != 0 ? p[1] : p[2]);
+  const int right = first > 0;
+  const int32_t e[3] = {right ? p[0] : -p[0], right ? p[1] : -p[1], right ? p[2] : -p[2]};
+  double q[5], qL[5], qR[5];
+  for (int32_t m = -2; m <= 2; ++m)
+    q[m + 2] = Tf[((t[2] + m * e[2]) * TW + (t[1] + m * e[1])) * TW + (t[0] + m * e[0])];
+  oracle_ppm_1d(q, 5, qL, qR);
+  return right ? qR[2] : qL[2];
+}
+
+/* Flux through the face normal to d between tile cells tl and tl + d: the
+ * Kurganov-Tadmor flux at its 9 points (pu, pv) in {-1,0,1}^2 (u < v the
+ * other two axes), the left state from cell tl at offset (+1, pu, pv)/2 and
+ * the right state from cell tl + d at offset (-1, pu, pv)/2, combined by the
+ * tensor-product Simpson rule, weights 1 (corners), 4 (edge midpoints) and
+ * 16 (centre) over 36, summed as
+ *   ((corners + 4 edges) + 16 centre) / 36,
+ *   corners = (H(-1,-1) + H(1,1)) + (H(1,-1) + H(-1,1)),
+ *   edges   = (H(0,-1) + H(0,1)) + (H(-1,0) + H(1,0)),
+ * an order that a mirror of either transverse axis only commutes.  Returns
+ * the number of unphysical states seen. */
+int oracle_face_flux_3d(const ogrid* g, const double* T, int d, const int32_t tl[3],
+                        double* H) {
+  const int nf = g->nf;
+  const int u = d == 0 ? 1 : 0, v = d == 2 ? 1 : 2;
+  int32_t tr[3] = {tl[0], tl[1], tl[2]};
+  tr[d] += 1;
+  double Hp[3][3][ORACLE_MAX_NF]; /* [pv + 1][pu + 1][field] */
+  double UL[ORACLE_MAX_NF], UR[ORACLE_MAX_NF];
+  int bad = 0;
+  for (int32_t pv = -1; pv <= 1; ++pv)
+    for (int32_t pu = -1; pu <= 1; ++pu) {
+      int32_t pl[3], pr[3];
+      pl[d] = 1;
+      pr[d] = -1;
+      pl[u] = pr[u] = pu;
+      pl[v] = pr[v] = pv;
+      for (int f = 0; f < nf; ++f) {
+        UL[f] = oracle_point_value(T + (size_t)f * TILE, tl, pl);
+        UR[f] = oracle_point_value(T + (size_t)f * TILE, tr, pr);
+      }
+      bad += oracle_face_flux(d, nf, UL, UR, g->gamma, g->eta1, Hp[pv + 1][pu + 1]);
+    }
+  for (int f = 0; f < nf; ++f) {
+#define HP(a, b) Hp[(b) + 1][(a) + 1][f]
+    const double corners = (HP(-1, -1) + HP(1, 1)) + (HP(1, -1) + HP(-1, 1));
+    const double edges = (HP(0, -1) + HP(0, 1)) + (HP(-1, 0) + HP(1, 0));
+    H[f] = ((corners + 4.0 * edges) + 16.0 * HP(0, 0)) / 36.0;
+#undef HP
+  }
+  return bad;
+}
+
 /* Position of transverse cell (u, v) in a face normal to d: u, v are the
  * two other axes in increasing order (d=0: y,z; d=1: x,z; d=2: x,y). */
 static int32_t face_index(int32_t u, int32_t v) { return u + SUB * v; }
@@ -432,6 +499,14 @@ int64_t oracle_step_record(const ogrid* g, const double* U0, const double* Uk, d
             }
             /* face k+1/2 between tile cells k and k+1, k = 2..10 */
             for (int32_t k = GH - 1; k < GH + SUB; ++k) {
+              if (g->recon == 1) {
+                int32_t tl[3];
+                tl[d] = k;
+                tl[(d + 1) % 3] = a + GH;
+                tl[(d + 2) % 3] = b + GH;
+                bad_total += oracle_face_flux_3d(g, T, d, tl, H[k]);
+                continue;
+              }
               for (int f = 0; f < nf; ++f) {
                 UL[f] = pR[f][k];
                 UR[f] = pL[f][k + 1];

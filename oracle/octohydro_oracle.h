@@ -20,6 +20,8 @@ typedef struct {
   const int32_t* children; /* [n_nodes][8] */
   double gamma, eta1;
   double omega; /* frame angular velocity about the z axis through (0.5, 0.5) */
+  int32_t recon; /* 0: PPM per axis, flux at the face centre;
+                    1: 3D reconstruction, 9-point Simpson flux per face */
 } ogrid;
 
 int oracle_build_table(int32_t n_leaves, int32_t base, const int32_t* leaf_coord, int32_t* nbr,
@@ -50,6 +52,13 @@ int64_t oracle_rk3_step(const ogrid* g, double* U, double* W1, double* W2, doubl
                         double dt_in, double* dt_out);
 int64_t oracle_step_1d(int32_t n, int nf, const double* U0, const double* Uk, double* Uout,
                        double dt, double beta, double gamma, double eta1);
+
+/* 3D reconstruction (recon = 1): value of one field's 14^3 tile Tf at the
+ * point t + p/2 of tile cell t (p in {-1,0,1}^3, not 0), and the 9-point
+ * Simpson flux of the face normal to d between tile cells tl and tl + d
+ * (T = nf consecutive tiles). */
+double oracle_point_value(const double* Tf, const int32_t t[3], const int32_t p[3]);
+int oracle_face_flux_3d(const ogrid* g, const double* T, int d, const int32_t tl[3], double* H);
 
 int oracle_num_threads(void);
 
