@@ -70,10 +70,27 @@ extern "C" {
 #define HYDRO_STATUS_UNPHYSICAL 1u
 #define HYDRO_STATUS_TABLE 2u
 
+/* reconstruction (Sec. V-B-1)
+ *  HYDRO_RECON_AXIS  PPM along each axis, Kurganov-Tadmor flux at the face
+ *                    centre (the default).
+ *  HYDRO_RECON_3D    full three-dimensional reconstruction: values at the 26
+ *                    face, edge and corner points of each cell from the same
+ *                    PPM along the 13 lines of cells through it (5 cells each;
+ *                    a point p/2 comes from the line along p or -p, whichever
+ *                    has its first non-zero component positive), and per face
+ *                    the Kurganov-Tadmor flux at its 9 points combined by the
+ *                    tensor Simpson rule ((corners + 4 edges) + 16 centre)/36
+ *                    with corners = (H(-1,-1)+H(1,1)) + (H(1,-1)+H(-1,1)) and
+ *                    edges = (H(0,-1)+H(0,1)) + (H(-1,0)+H(1,0)).  Needs
+ *                    ghost_tile_dev. */
+#define HYDRO_RECON_AXIS 0
+#define HYDRO_RECON_3D 1
+
 /* flags */
 #define HYDRO_FLAG_VALIDATE 1u  /* check table ids on the device and wait    */
-#define HYDRO_FLAG_NODES_READY 2u /* node_state_dev already holds the restricted
-                                     copies of this call's Uk: skip them      */
+#define HYDRO_FLAG_NODES_READY 2u /* node_state_dev (or ghost_tile_dev in the 3D
+                                     mode) already holds this call's Uk: skip
+                                     making it                                */
 
 /*
  * A batch of leaves (Sec. IV-C): host struct, device arrays.
@@ -98,8 +115,8 @@ typedef struct hydro_grid {
   int32_t n_nodes;
   int32_t n_fields;
   int32_t dtype;
-  int32_t base; /* level-0 sub-grids per axis */
-  int32_t reserved;
+  int32_t base;           /* level-0 sub-grids per axis */
+  int32_t reconstruction; /* HYDRO_RECON_AXIS (0) or HYDRO_RECON_3D (1) */
   const int32_t* leaf_coord_dev;
   const int32_t* nbr_dev;
   const uint8_t* nbr_kind_dev;
@@ -143,6 +160,11 @@ typedef struct hydro_grid {
    * of refined face neighbours from it.  Two calls that run at the same
    * time need two buffers. */
   void* node_state_dev;
+  /* Materialised ghosted tiles for reconstruction = HYDRO_RECON_3D:
+   * caller-owned device scratch of n_fields * n_leaves * 14^3 elements of
+   * `dtype`, laid out like the output of hydro_fill_ghosts; required in that
+   * mode, ignored otherwise.  Every 3D substep fills it from its Uk. */
+  void* ghost_tile_dev;
 } hydro_grid;
 
 /*
@@ -196,11 +218,12 @@ int hydro_fill_ghosts(const hydro_grid* grid, const void* U_dev, void* G_dev, vo
  * of the 4 fine fluxes and Hc its own, and Uout -= w dt q on its high face,
  * += on its low face (w = 1 without U0, else beta; faces x, y, z, low first).
  * Before the fluxes, the restricted copies of the refined nodes are made
- * from Uk into grid->node_state_dev (when the tree has refined nodes).
- * Uout_dev may alias neither Uk_dev nor U0_dev.  flags: HYDRO_FLAG_VALIDATE;
- * HYDRO_FLAG_NODES_READY when the node copies were made from this Uk by an
- * earlier call and not overwritten since (the caller's promise: it is not
- * checked).
+ * from Uk into grid->node_state_dev (when the tree has refined nodes), or,
+ * with reconstruction HYDRO_RECON_3D, the ghosted tiles of Uk into
+ * grid->ghost_tile_dev.  Uout_dev may alias neither Uk_dev nor U0_dev.
+ * flags: HYDRO_FLAG_VALIDATE; HYDRO_FLAG_NODES_READY when that scratch was
+ * made from this Uk by an earlier call and not overwritten since (the
+ * caller's promise: it is not checked).
  */
 int hydro_step(const hydro_grid* grid, const void* U0_dev, const void* Uk_dev, void* Uout_dev,
                const double* dt_dev, double beta, uint32_t flags, void* stream);

@@ -28,6 +28,7 @@ HYDRO_F64, HYDRO_F32 = 0, 1
 HYDRO_SAME_LEAF, HYDRO_SAME_REFINED, HYDRO_COARSER_LEAF = 0, 1, 2
 HYDRO_FLAG_VALIDATE = 1
 HYDRO_FLAG_NODES_READY = 2
+HYDRO_RECON_AXIS, HYDRO_RECON_3D = 0, 1
 HYDRO_MAX_LEAVES = 1048575
 HYDRO_STATUS_UNPHYSICAL, HYDRO_STATUS_TABLE = 1, 2
 
@@ -53,7 +54,7 @@ class hydro_grid(ctypes.Structure):
         ("n_fields", ctypes.c_int32),
         ("dtype", ctypes.c_int32),
         ("base", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("reconstruction", ctypes.c_int32),
         ("leaf_coord_dev", ctypes.c_void_p),
         ("nbr_dev", ctypes.c_void_p),
         ("nbr_kind_dev", ctypes.c_void_p),
@@ -69,6 +70,7 @@ class hydro_grid(ctypes.Structure):
         ("flux_reg_dev", ctypes.c_void_p),
         ("omega", ctypes.c_double),
         ("node_state_dev", ctypes.c_void_p),
+        ("ghost_tile_dev", ctypes.c_void_p),
     ]
 
 
@@ -206,7 +208,8 @@ class Grid:
     correction."""
 
     def __init__(self, leaf_coord, base, n_fields, dtype=HYDRO_F64, gamma=5.0 / 3.0,
-                 eta1=1e-3, device="cuda", reflux=False, omega=0.0):
+                 eta1=1e-3, device="cuda", reflux=False, omega=0.0,
+                 reconstruction=HYDRO_RECON_AXIS):
         coord = np.ascontiguousarray(leaf_coord, dtype=np.int32)
         nbr, kind, kids = hydro_build_table(coord, base)
         self.host_nbr, self.host_kind, self.host_children = nbr, kind, kids
@@ -223,12 +226,18 @@ class Grid:
         self.torch_dtype = torch.float64 if dtype == HYDRO_F64 else torch.float32
         self.c = hydro_grid(
             n_leaves=self.n_leaves, n_nodes=len(kids), n_fields=self.n_fields, dtype=self.dtype,
-            base=self.base, reserved=0, leaf_coord_dev=self.coord.data_ptr(),
+            base=self.base, reconstruction=int(reconstruction),
+            leaf_coord_dev=self.coord.data_ptr(),
             nbr_dev=self.nbr.data_ptr(), nbr_kind_dev=self.kind.data_ptr(),
             children_dev=self.children.data_ptr(), status_dev=self.status.data_ptr(),
             gamma=float(gamma), dual_energy_eta1=float(eta1), omega=float(omega))
-        # scratch for the restricted copies of the refined blocks
-        if len(kids):
+        # scratch of the reconstruction: materialised ghosted tiles (3D), or
+        # the restricted copies of the refined blocks
+        if reconstruction == HYDRO_RECON_3D:
+            self.ghost_tiles = torch.empty((self.n_fields, self.n_leaves, 14, 14, 14),
+                                           dtype=self.torch_dtype, device=dev)
+            self.c.ghost_tile_dev = self.ghost_tiles.data_ptr()
+        elif len(kids):
             self.node_state = torch.empty((self.n_fields, len(kids), 8, 8, 8),
                                           dtype=self.torch_dtype, device=dev)
             self.c.node_state_dev = self.node_state.data_ptr()

@@ -921,6 +921,219 @@ __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
 }
 
 // ---------------------------------------------------------------------------
+// Full three-dimensional reconstruction with face quadrature (Sec. V-B-1: the
+// reconstruct kernel does a full 3D reconstruction, the flux kernel integrates
+// each face's flux by quadrature).
+//
+// Each cell gets values at its 26 face, edge and corner points: the point
+// t + p/2 (p in {-1,0,1}^3, not 0) comes from the PPM of the axis scheme on
+// the 5 cells t + m e, m = -2..2, with e = p or -p (first non-zero component
+// positive): the right end of the cell's parabola when e = p, else the left
+// end.  A face normal to D gets the Kurganov-Tadmor flux at its 9 points
+// (pu, pv) in {-1,0,1}^2 (u < v the other two axes) -- left state from the
+// left cell at (+1, pu, pv)/2, right state from the right cell at
+// (-1, pu, pv)/2 -- combined by the tensor Simpson rule
+//   ((corners + 4 edges) + 16 centre) / 36,
+//   corners = (H(-1,-1) + H(1,1)) + (H(1,-1) + H(-1,1)),
+//   edges   = (H(0,-1) + H(0,1)) + (H(-1,0) + H(1,0)).
+//
+// Ghost cells come from tiles materialised by k_fill (all 26 regions: the
+// diagonal lines reach edge and corner ghosts).  One wave per leaf and one
+// phase per axis D; lane (u, v) owns the pencil along D through transverse
+// cell (u, v) and evaluates its 9 faces in turn.  The flux differences meet
+// in an LDS accumulator in the order ((x + y) + z); the z phase finishes the
+// cells exactly as k_step does.
+// ---------------------------------------------------------------------------
+
+// One end of the PPM parabola of the cell at t along a line of tile stride s.
+template <typename T>
+__device__ __forceinline__ T line_end(const T* __restrict__ t, int s, bool right) {
+  const T q0 = t[-2 * s], q1 = t[-s], q2 = t[0], q3 = t[s], q4 = t[2 * s];
+  const T dm1 = limited_slope(q0, q1, q2);
+  const T dm2 = limited_slope(q1, q2, q3);
+  const T dm3 = limited_slope(q2, q3, q4);
+  T l = T(0.5) * (q1 + q2) - (dm2 - dm1) * T(1.0 / 6.0);
+  T r = T(0.5) * (q2 + q3) - (dm3 - dm2) * T(1.0 / 6.0);
+  monotonise(q2, l, r);
+  return right ? r : l;
+}
+
+// Tile stride of the line that gives point p, and whether p is its right end.
+struct PointLine {
+  int s;
+  bool right;
+};
+
+__device__ __forceinline__ constexpr PointLine point_line(int px, int py, int pz) {
+  return PointLine{((px != 0 ? px : (py != 0 ? py : pz)) > 0 ? 1 : -1) *
+                       (px + TW * py + TW * TW * pz),
+                   (px != 0 ? px : (py != 0 ? py : pz)) > 0};
+}
+
+// Point offset components of face point (pu, pv) on side sd (+1 left cell,
+// -1 right cell) of a face normal to D.
+template <int D>
+__device__ __forceinline__ constexpr PointLine face_point(int sd, int pu, int pv) {
+  return D == 0 ? point_line(sd, pu, pv) : (D == 1 ? point_line(pu, sd, pv)
+                                                   : point_line(pu, pv, sd));
+}
+
+// Simpson combination of the 9 point values of one field, points in the
+// order (-1,-1), (1,1), (1,-1), (-1,1), (0,-1), (0,1), (-1,0), (1,0), (0,0).
+template <typename T>
+__device__ __forceinline__ T simpson9(const T (&h)[9]) {
+  const T corners = (h[0] + h[1]) + (h[2] + h[3]);
+  const T edges = (h[4] + h[5]) + (h[6] + h[7]);
+  return ((corners + T(4) * edges) + T(16) * h[8]) / T(36);
+}
+
+// Flux of all fields through the face between tile cells tl and tl + stride
+// of D (Gt: field 0's tile of the leaf, field stride fsG).
+template <typename T, int NF, int D>
+__device__ __forceinline__ void face_flux_3d(const Phys<T>& ph, const T* __restrict__ Gt,
+                                             size_t fsG, int tl, T (&H)[NF], bool& bad) {
+  constexpr int SD = D == 0 ? 1 : (D == 1 ? TW : TW * TW);
+  constexpr int PU[9] = {-1, 1, 1, -1, 0, 0, -1, 1, 0};
+  constexpr int PV[9] = {-1, 1, -1, 1, -1, 1, 0, 0, 0};
+  const int tr = tl + SD;
+  T hc[NF_CORE][9], vl[9], vr[9], ha[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const PointLine pl = face_point<D>(1, PU[q], PV[q]);
+    const PointLine pr = face_point<D>(-1, PU[q], PV[q]);
+    T UL[NF_CORE], UR[NF_CORE], Hc[NF_CORE];
+#pragma unroll
+    for (int f = 0; f < NF_CORE; ++f) {
+      UL[f] = line_end(Gt + f * fsG + tl, pl.s, pl.right);
+      UR[f] = line_end(Gt + f * fsG + tr, pr.s, pr.right);
+    }
+    core_flux(ph, D, UL, UR, Hc, vl[q], vr[q], ha[q], bad);
+#pragma unroll
+    for (int f = 0; f < NF_CORE; ++f) hc[f][q] = Hc[f];
+  }
+#pragma unroll
+  for (int f = 0; f < NF_CORE; ++f) H[f] = simpson9(hc[f]);
+#pragma unroll
+  for (int f = NF_CORE; f < NF; ++f) {
+    T h[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const PointLine pl = face_point<D>(1, PU[q], PV[q]);
+      const PointLine pr = face_point<D>(-1, PU[q], PV[q]);
+      const T ul = line_end(Gt + f * fsG + tl, pl.s, pl.right);
+      const T ur = line_end(Gt + f * fsG + tr, pr.s, pr.right);
+      h[q] = T(0.5) * (ul * vl[q] + ur * vr[q]) - ha[q] * (ur - ul);
+    }
+    H[f] = simpson9(h);
+  }
+}
+
+// Phase D of the 3D step: lane (u, v) walks the 9 faces of its pencil.
+template <typename T, int NF, int D>
+__device__ __forceinline__ void phase3d(const StepArgs& s, const Phys<T>& ph,
+                                        const LeafInfo& li, const T* __restrict__ G,
+                                        double* __restrict__ acc, int lane, double dt,
+                                        double inv_dx, bool& bad) {
+  constexpr int U = D == 0 ? 1 : 0, V = D == 2 ? 1 : 2;
+  constexpr int ST[3] = {1, TW, TW * TW};
+  const GridArgs& g = s.g;
+  const int u = lane & 7, v = lane >> 3;
+  const size_t fsG = (size_t)g.n_leaves * TILE;
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const T* __restrict__ Gt = G + (size_t)li.leaf * TILE;
+  const int t0 = (u + GH) * ST[U] + (v + GH) * ST[V];
+  FaceNbr fn;
+  fn.klo = fn.ilo = fn.khi = fn.ihi = 0;
+  fn.rlo = fn.rhi = fn.flo = fn.fhi = -1;
+  if (g.reg) {
+    fn.rlo = g.face_slot[6 * li.leaf + 2 * D];
+    fn.rhi = g.face_slot[6 * li.leaf + 2 * D + 1];
+    fn.flo = g.fine_slot[6 * li.leaf + 2 * D];
+    fn.fhi = g.fine_slot[6 * li.leaf + 2 * D + 1];
+  }
+  double Hprev[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) Hprev[f] = 0.0;
+#pragma unroll 1
+  for (int k = GH - 1; k < GH + SUB; ++k) {
+    const int tl = t0 + k * ST[D];
+    T H[NF];
+    face_flux_3d<T, NF, D>(ph, Gt, fsG, tl, H, bad);
+    if (g.reg && (k == GH - 1 || k == GH + SUB - 1))
+      record_face<T, NF>(g, fn, k == GH - 1 ? 0 : 8, u, v, H);
+    if (k >= GH) {
+      const int i = k - GH;  // interior cell along D: H is its high face
+      int l[3];
+      l[D] = i;
+      l[U] = u;
+      l[V] = v;
+      const int cell = l[2] * 64 + l[1] * 8 + l[0];
+      if (D == 0) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f * CELLS + cell] = (double)H[f] - Hprev[f];
+      } else if (D == 1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          acc[f * CELLS + cell] = acc[f * CELLS + cell] + ((double)H[f] - Hprev[f]);
+      } else {
+        double src[4] = {0.0, 0.0, 0.0, 0.0};
+        const bool rot = g.omega != 0.0;
+        const T* __restrict__ ukc = Gt + tl;  // this cell's Uk (tile centre of cell k)
+        if (rot) {
+          const double dx = 1.0 / (double)(SUB * li.blocks);
+          const double rx = ((double)(SUB * li.ix + u) + 0.5) * dx - 0.5;
+          const double ry = ((double)(SUB * li.iy + v) + 0.5) * dx - 0.5;
+          const double rho = (double)ukc[0], sx = (double)ukc[fsG], sy = (double)ukc[2 * fsG];
+          const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+          src[0] = tw * sy + rho * om2 * rx;
+          src[1] = rho * om2 * ry - tw * sx;
+          src[3] = om2 * (sx * rx + sy * ry);
+        }
+        const uint32_t at = (uint32_t)li.leaf * CELLS + cell;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const double sum = acc[f * CELLS + cell] + ((double)H[f] - Hprev[f]);
+          const T u0 = s.U0 ? static_cast<const T*>(s.U0)[(size_t)f * fs + at] : T(0);
+          finish_cell<T>(s, (size_t)f * fs, at, ukc[f * fsG], u0, sum, rot && f >= 1 && f <= 4,
+                         f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) Hprev[f] = (double)H[f];
+  }
+}
+
+template <typename T, int NF>
+__global__ void __launch_bounds__(64) k_step3d(StepArgs s, const T* __restrict__ G) {
+  __shared__ double acc[NF * CELLS];
+  const GridArgs& g = s.g;
+  const int leaf = s.leaf_base + blockIdx.x;
+  if (leaf >= g.n_leaves) return;
+  const int lane = threadIdx.x;
+  LeafInfo li;
+  li.leaf = leaf;
+  const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
+  li.ix = c4.y;
+  li.iy = c4.z;
+  li.iz = c4.w;
+  li.blocks = g.base << c4.x;
+  const double dt = *s.dt;
+  const double inv_dx = (double)(SUB * li.blocks);
+  Phys<T> ph;
+  ph.gamma = (T)g.gamma;
+  ph.gm1 = (T)(g.gamma - 1.0);
+  ph.eta1 = (T)g.eta1;
+  bool bad = false;
+  phase3d<T, NF, 0>(s, ph, li, G, acc, lane, dt, inv_dx, bad);
+  __syncthreads();
+  phase3d<T, NF, 1>(s, ph, li, G, acc, lane, dt, inv_dx, bad);
+  __syncthreads();
+  phase3d<T, NF, 2>(s, ph, li, G, acc, lane, dt, inv_dx, bad);
+  if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
+}
+
+// ---------------------------------------------------------------------------
 // Coarse-fine flux correction: one launch per face orientation o, one thread
 // per (slot, field, coarse face cell); a coarse leaf has at most one slot per
 // orientation, so no two threads of a launch touch the same value.
@@ -1124,6 +1337,8 @@ static int check_grid(const hydro_grid* gr, const char* fn) {
   if (gr->dtype != HYDRO_F64 && gr->dtype != HYDRO_F32)
     return fail(HYDRO_E_ARG, "%s: unknown dtype %d", fn, gr->dtype);
   if (gr->base <= 0) return fail(HYDRO_E_ARG, "%s: base must be positive", fn);
+  if (gr->reconstruction != HYDRO_RECON_AXIS && gr->reconstruction != HYDRO_RECON_3D)
+    return fail(HYDRO_E_ARG, "%s: unknown reconstruction %d", fn, gr->reconstruction);
   if (!gr->leaf_coord_dev || !gr->nbr_dev || !gr->nbr_kind_dev)
     return fail(HYDRO_E_ARG, "%s: table pointers must be set", fn);
   if (gr->n_nodes > 0 && !gr->children_dev)
@@ -1195,6 +1410,21 @@ static int grid_blocks(int64_t work, int threads, int cap) {
   return (int)(b < 1 ? 1 : b);
 }
 
+// Ghosted 14^3 tiles of U into G (all 26 ghost regions).
+static int fill_launch(const hydro_grid* gr, const void* U, void* G, hipStream_t st) {
+  const GridArgs g = grid_args(gr);
+  const int64_t total = (int64_t)g.nf * g.n_leaves * TILE;
+  const int blocks = grid_blocks(total, 256, 1 << 16);
+  if (gr->dtype == HYDRO_F64)
+    hipLaunchKernelGGL(k_fill<double>, dim3(blocks), dim3(256), 0, st, g,
+                       static_cast<const double*>(U), static_cast<double*>(G), total);
+  else
+    hipLaunchKernelGGL(k_fill<float>, dim3(blocks), dim3(256), 0, st, g,
+                       static_cast<const float*>(U), static_cast<float*>(G), total);
+  HIP_TRY(hipGetLastError());
+  return HYDRO_OK;
+}
+
 // The restricted node copies of a substep's input state (nothing without
 // refined nodes).
 static int restrict_launch(const hydro_grid* gr, const void* Uk, hipStream_t st) {
@@ -1252,6 +1482,26 @@ static hipError_t launch_step_t(const StepArgs& a, int blocks, int waves, hipStr
   }
 }
 
+template <typename T>
+static hipError_t launch_step3d_t(const StepArgs& a, int blocks, const T* G, hipStream_t st) {
+  switch (a.g.nf) {
+#define OCTOHYDRO_CASE3D(n) \
+  case n: hipLaunchKernelGGL((k_step3d<T, n>), dim3(blocks), dim3(64), 0, st, a, G); break;
+    OCTOHYDRO_CASE3D(6) OCTOHYDRO_CASE3D(7) OCTOHYDRO_CASE3D(8) OCTOHYDRO_CASE3D(9)
+    OCTOHYDRO_CASE3D(10) OCTOHYDRO_CASE3D(11) OCTOHYDRO_CASE3D(12) OCTOHYDRO_CASE3D(13)
+    OCTOHYDRO_CASE3D(14) OCTOHYDRO_CASE3D(15) OCTOHYDRO_CASE3D(16)
+#undef OCTOHYDRO_CASE3D
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+static hipError_t launch_step3d(const StepArgs& a, int dtype, int blocks, const void* G,
+                                hipStream_t st) {
+  return dtype == HYDRO_F64 ? launch_step3d_t<double>(a, blocks, static_cast<const double*>(G), st)
+                            : launch_step3d_t<float>(a, blocks, static_cast<const float*>(G), st);
+}
+
 static hipError_t launch_step(StepArgs a, int dtype, int blocks, hipStream_t st) {
   const Options o = get_options(dtype, a.g.nf);
   if (a.remap) a.remap = o.xcd_remap;
@@ -1283,7 +1533,12 @@ static int step_common(const hydro_grid* gr, const void* U0, const void* Uk, voi
     return fail(HYDRO_E_ARG, "%s: Uout may not alias an input", fn);
   if (flags & ~(HYDRO_FLAG_VALIDATE | HYDRO_FLAG_NODES_READY))
     return fail(HYDRO_E_ARG, "%s: unknown flags", fn);
-  if (gr->n_nodes > 0) {
+  if (gr->reconstruction == HYDRO_RECON_3D) {
+    if (!gr->ghost_tile_dev)
+      return fail(HYDRO_E_ARG, "%s: ghost_tile_dev is NULL but reconstruction is 3D", fn);
+    if (gr->ghost_tile_dev == Uk || gr->ghost_tile_dev == Uout || (U0 && gr->ghost_tile_dev == U0))
+      return fail(HYDRO_E_ARG, "%s: ghost_tile_dev may not alias a state array", fn);
+  } else if (gr->n_nodes > 0) {
     if (!gr->node_state_dev)
       return fail(HYDRO_E_ARG, "%s: node_state_dev is NULL but n_nodes > 0", fn);
     const uint64_t node_bytes = (uint64_t)gr->n_fields * (uint64_t)gr->n_nodes * CELLS *
@@ -1320,6 +1575,22 @@ static int cfl_launch(const hydro_grid* gr, const void* U, double cfl, double* d
   return HYDRO_OK;
 }
 
+// One substep on `st`: the pre-pass of the reconstruction (restricted node
+// copies, or the materialised tiles of the 3D mode), the step kernel over
+// `blocks` leaves from a.leaf_base, and nothing else.
+static int substep_kernels(const hydro_grid* gr, const StepArgs& a, int blocks, bool pre,
+                           hipStream_t st) {
+  int rc;
+  if (gr->reconstruction == HYDRO_RECON_3D) {
+    if (pre && (rc = fill_launch(gr, a.Uk, gr->ghost_tile_dev, st))) return rc;
+    HIP_TRY(launch_step3d(a, gr->dtype, blocks, gr->ghost_tile_dev, st));
+    return HYDRO_OK;
+  }
+  if (pre && (rc = restrict_launch(gr, a.Uk, st))) return rc;
+  HIP_TRY(launch_step(a, gr->dtype, blocks, st));
+  return HYDRO_OK;
+}
+
 static int rk3_launch(const hydro_grid* gr, const void* Un, void* W1, void* W2, void* Unext,
                       double cfl, double* dt, hipStream_t st) {
   int rc = check_grid(gr, "hydro_rk3_step");
@@ -1336,21 +1607,18 @@ static int rk3_launch(const hydro_grid* gr, const void* Un, void* W1, void* W2, 
     rc = cfl_launch(gr, Un, cfl, dt, st);
     if (rc) return rc;
   }
-  if ((rc = restrict_launch(gr, Un, st))) return rc;
-  HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
+  if ((rc = substep_kernels(gr, a, gr->n_leaves, true, st))) return rc;
   if ((rc = reflux_launch(gr, a, st))) return rc;
   a.U0 = Un;
   a.Uk = W1;
   a.Uout = W2;
   a.beta = 0.25;
-  if ((rc = restrict_launch(gr, W1, st))) return rc;
-  HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
+  if ((rc = substep_kernels(gr, a, gr->n_leaves, true, st))) return rc;
   if ((rc = reflux_launch(gr, a, st))) return rc;
   a.Uk = W2;
   a.Uout = Unext;
   a.beta = 2.0 / 3.0;
-  if ((rc = restrict_launch(gr, W2, st))) return rc;
-  HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
+  if ((rc = substep_kernels(gr, a, gr->n_leaves, true, st))) return rc;
   if ((rc = reflux_launch(gr, a, st))) return rc;
   return HYDRO_OK;
 }
@@ -1444,18 +1712,7 @@ int hydro_fill_ghosts(const hydro_grid* gr, const void* U, void* G, void* stream
   if (rc) return rc;
   if (!U || !G) return fail(HYDRO_E_ARG, "hydro_fill_ghosts: U and G must be set");
   if (U == G) return fail(HYDRO_E_ARG, "hydro_fill_ghosts: G may not alias U");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  GridArgs g = grid_args(gr);
-  const int64_t total = (int64_t)g.nf * g.n_leaves * TILE;
-  const int blocks = grid_blocks(total, 256, 1 << 16);
-  if (gr->dtype == HYDRO_F64)
-    hipLaunchKernelGGL(k_fill<double>, dim3(blocks), dim3(256), 0, st, g,
-                       static_cast<const double*>(U), static_cast<double*>(G), total);
-  else
-    hipLaunchKernelGGL(k_fill<float>, dim3(blocks), dim3(256), 0, st, g,
-                       static_cast<const float*>(U), static_cast<float*>(G), total);
-  HIP_TRY(hipGetLastError());
-  return HYDRO_OK;
+  return fill_launch(gr, U, G, static_cast<hipStream_t>(stream));
 }
 
 int hydro_step(const hydro_grid* gr, const void* U0, const void* Uk, void* Uout, const double* dt,
@@ -1469,8 +1726,8 @@ int hydro_step(const hydro_grid* gr, const void* U0, const void* Uk, void* Uout,
     rc = validate_table(gr, st);
     if (rc) return rc;
   }
-  if (!(flags & HYDRO_FLAG_NODES_READY) && (rc = restrict_launch(gr, Uk, st))) return rc;
-  HIP_TRY(launch_step(a, gr->dtype, gr->n_leaves, st));
+  if ((rc = substep_kernels(gr, a, gr->n_leaves, !(flags & HYDRO_FLAG_NODES_READY), st)))
+    return rc;
   return reflux_launch(gr, a, st);
 }
 
@@ -1501,14 +1758,19 @@ int hydro_step_per_leaf(const hydro_grid* gr, const void* U0, const void* Uk, vo
     HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     g_pool.events.push_back(e);
   }
-  if ((rc = restrict_launch(gr, Uk, st))) return rc;
+  // the pre-pass of the reconstruction runs once, on `stream`
+  if (gr->reconstruction == HYDRO_RECON_3D) {
+    if ((rc = fill_launch(gr, Uk, gr->ghost_tile_dev, st))) return rc;
+  } else if ((rc = restrict_launch(gr, Uk, st))) {
+    return rc;
+  }
   // pool streams start after the work already queued on `stream`
   HIP_TRY(hipEventRecord(g_pool.events[0], st));
   for (int i = 0; i < n_streams; ++i) HIP_TRY(hipStreamWaitEvent(g_pool.streams[i], g_pool.events[0], 0));
   a.remap = 0;
   for (int leaf = 0; leaf < gr->n_leaves; ++leaf) {
     a.leaf_base = leaf;
-    HIP_TRY(launch_step(a, gr->dtype, 1, g_pool.streams[leaf % n_streams]));
+    if ((rc = substep_kernels(gr, a, 1, false, g_pool.streams[leaf % n_streams]))) return rc;
   }
   for (int i = 0; i < n_streams; ++i) {
     HIP_TRY(hipEventRecord(g_pool.events[i], g_pool.streams[i]));

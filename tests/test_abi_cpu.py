@@ -95,7 +95,7 @@ def test_table_rejects_bad_trees(hb):
 
 
 def _raw_grid(hb, **kw):
-    g = hb.hydro_grid(n_leaves=8, n_nodes=0, n_fields=6, dtype=0, base=2, reserved=0,
+    g = hb.hydro_grid(n_leaves=8, n_nodes=0, n_fields=6, dtype=0, base=2, reconstruction=0,
                       leaf_coord_dev=16, nbr_dev=16, nbr_kind_dev=16, children_dev=None,
                       status_dev=None, gamma=5.0 / 3.0, dual_energy_eta1=1e-3)
     for k, v in kw.items():
@@ -212,3 +212,17 @@ def test_grid_size_limits_are_checked_on_the_host(hb):
     g = _raw_grid(hb, n_leaves=65536, n_fields=16)
     assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
     assert "4 GiB" in hb.hydro_last_error()
+
+
+def test_reconstruction_mode_is_checked_on_the_host(hb):
+    lib = hb._lib
+    a, b = ctypes.c_void_p(64), ctypes.c_void_p(128)
+    g = _raw_grid(hb, reconstruction=2)
+    assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
+    assert "reconstruction" in hb.hydro_last_error()
+    g = _raw_grid(hb, reconstruction=hb.HYDRO_RECON_3D)
+    assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
+    assert "ghost_tile_dev" in hb.hydro_last_error()
+    g = _raw_grid(hb, reconstruction=hb.HYDRO_RECON_3D, ghost_tile_dev=64)
+    assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
+    assert "alias" in hb.hydro_last_error()
