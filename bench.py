@@ -47,6 +47,26 @@ def ops_per_leaf_stage(nf: int, with_u0: bool) -> int:
     return 3 * 64 * per_pencil + 512 * nf * per_cell_field
 
 
+# Distinct (cell, line) reconstructions one leaf's faces need in the 3D
+# reconstruction: 13 lines through each interior cell plus the lines of the
+# ghost cells next to the leaf's faces (counted by enumerating, for every
+# face point and side, the cell and the line that give its value).
+LINES_PER_LEAF_3D = 10112
+
+
+def ops_per_leaf_stage_3d(nf: int, with_u0: bool) -> int:
+    """Operations of one substep of one leaf with the full 3D reconstruction,
+    counted like ops_per_leaf_stage on the method's minimal evaluation:
+      one PPM per (cell, line) giving both ends: 3 limited slopes x 10 +
+        2 interface values x 5 + 1 monotonised cell x 18 = 58 per field;
+      per face point: the Kurganov-Tadmor flux, 80 + 7 per species;
+      per face and field: the Simpson combination, 11;
+      per cell and field: the update as in the axis scheme."""
+    per_face = 9 * (80 + 7 * (nf - 6)) + 11 * nf
+    per_cell_field = 8 + (3 if with_u0 else 0)
+    return LINES_PER_LEAF_3D * nf * 58 + 3 * 576 * per_face + 512 * nf * per_cell_field
+
+
 def hbm_bytes_per_leaf_stage(nf: int, w: int, with_u0: bool) -> int:
     """Algorithmic HBM bytes of one substep of one leaf: read Uk (+ U0),
     write Uout; halo re-reads are cache traffic, not counted."""
@@ -102,6 +122,49 @@ def time_rk3(torch, hb, w, dtype, steps, warmup):
     del A, B, W1, W2
     torch.cuda.empty_cache()
     return gpu_ms / steps, wall * 1e3 / steps, step_ms
+
+
+def time_rk3_3d(torch, hb, w, steps, warmup):
+    """FP64 RK3 steps with the full 3D reconstruction (HIP graph), and the
+    3D substep kernel alone in its later-stage form (events; the ghosted
+    tiles of the input are made once and reused with NODES_READY)."""
+    grid = hb.Grid(w.leaf_coord, w.base, w.nf, hb.HYDRO_F64, reconstruction=hb.HYDRO_RECON_3D)
+    A = torch.from_numpy(w.U).to("cuda").contiguous()
+    B, W1, W2 = grid.empty_state(), grid.empty_state(), grid.empty_state()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gAB = hb.Rk3Graph(grid, A, W1, W2, B, w.cfl, dt)
+    gBA = hb.Rk3Graph(grid, B, W1, W2, A, w.cfl, dt)
+    for i in range(warmup):
+        (gAB if i % 2 == 0 else gBA).launch()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for i in range(steps):
+        (gAB if (warmup + i) % 2 == 0 else gBA).launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    if hb.hydro_check_status(grid) != hb.HYDRO_OK:
+        raise RuntimeError(f"3D step status: {hb.hydro_last_error()}")
+    a, b = _events(torch)
+    a.record()
+    hb.hydro_fill_ghosts(grid, W1, grid.ghost_tiles)
+    b.record()
+    durs = []
+    for _ in range(3):
+        c, d = _events(torch)
+        c.record()
+        hb.hydro_step(grid, A, W1, W2, dt, 0.25, flags=hb.HYDRO_FLAG_NODES_READY)
+        d.record()
+        durs.append((c, d))
+    torch.cuda.synchronize()
+    fill_ms = a.elapsed_time(b)
+    kms = sum(c.elapsed_time(d) for c, d in durs) / len(durs)
+    gAB.close()
+    gBA.close()
+    del A, B, W1, W2, grid
+    torch.cuda.empty_cache()
+    return ms, kms, fill_ms
 
 
 def per_leaf_vs_batched(torch, hb, w, reps=2):
@@ -207,6 +270,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-leaf", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the full 3D reconstruction (9-point face quadrature)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="launch only the FP64 substep (for counter collection)")
     args = ap.parse_args()
@@ -261,6 +326,19 @@ def main():
     roof = alu if alu["frac"] >= hbm["frac"] else hbm
     other = hbm if roof is alu else alu
 
+    recon3d = None
+    if not args.no_3d:
+        steps3 = max(1, min(args.steps, 2))
+        log(f"FP64 full 3D reconstruction: 1 warmup + {steps3} timed RK3 steps")
+        ms3, kms3, fill3 = time_rk3_3d(torch, hb, w, steps3, 1)
+        ops3 = ops_per_leaf_stage_3d(nf, True) * n
+        recon3d = {"value": cells / (ms3 * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms3,
+                   "steps": steps3,
+                   "kernel": "k_step3d<double,11> (3D reconstruction, 9-point Simpson flux)",
+                   "kernel_ms": kms3, "ghost_fill_ms": fill3, "ops_per_launch": ops3,
+                   "alu_frac": ops3 / (kms3 * 1e-3) / ALU_PEAK,
+                   "hbm_frac": hbm_bytes_per_leaf_stage(nf, 8, True) * n / (kms3 * 1e-3) / HBM_PEAK}
+
     per_leaf = None
     if not args.no_per_leaf:
         log("batched vs per-leaf launches on the 21988-leaf octree")
@@ -286,6 +364,7 @@ def main():
         ("hbm" if roof is alu else "alu"): other,
         "hbm_frac_rk3_step": 8 * nf * 8 * cells / (ms64 * 1e-3) / HBM_PEAK,
         "fp32_mixed": fp32,
+        "recon_3d": recon3d,
         "per_leaf_vs_batched": per_leaf,
         "cpu_baseline": cpu,
     }
