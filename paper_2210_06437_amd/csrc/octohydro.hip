@@ -389,45 +389,6 @@ __device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo&
   return p;
 }
 
-// The Z phase re-reads the value of each cell it finishes (issued ahead with
-// the U0 loads) instead of carrying it through the recurrence.
-#ifndef OCTOHYDRO_Z_RELOAD
-#define OCTOHYDRO_Z_RELOAD 0
-#endif
-// Z phase: read the accumulator of the cell a step finishes at the top of
-// the step; load U0 of a step's cell one step ahead.
-#ifndef OCTOHYDRO_ACC_EARLY
-#define OCTOHYDRO_ACC_EARLY 0
-#endif
-#ifndef OCTOHYDRO_U0_AHEAD
-#define OCTOHYDRO_U0_AHEAD 0
-#endif
-#ifndef OCTOHYDRO_PROLOGUE_BATCH
-#define OCTOHYDRO_PROLOGUE_BATCH 0
-#endif
-#ifndef OCTOHYDRO_FENCE_RESTRICT
-#define OCTOHYDRO_FENCE_RESTRICT 0
-#endif
-#if OCTOHYDRO_FENCE_RESTRICT
-#define OCTOHYDRO_RFENCE() __builtin_amdgcn_sched_barrier(0)
-#else
-#define OCTOHYDRO_RFENCE() ((void)0)
-#endif
-
-// Element `off` of a field array whose base address is the same for every
-// lane.  The byte offset is formed in 32 bits (one field array is far below
-// 4 GiB), so the load takes the uniform base in scalar registers and one
-// 32-bit lane offset that all fields share.
-template <typename T>
-__device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
-                                     (uint32_t)(off * (uint32_t)sizeof(T)));
-}
-template <typename T>
-__device__ __forceinline__ void st(T* __restrict__ base, uint32_t off, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(off * (uint32_t)sizeof(T))) = v;
-}
-
 // Where stream position k (0..13) of a pencil comes from: a byte offset
 // into a field array and whether it is a refined ghost (mean of 8 cells).
 // Worked out once per stream step and shared by every field; for a step
@@ -469,7 +430,6 @@ constexpr int RSRC_WORD3 = 0x00020000;  // raw dword data format (gfx9 family)
 __device__ __forceinline__ Rsrc state_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, RSRC_WORD3);
 }
-
 
 // Field view: the array's resource and the field's scalar byte offset.
 struct FieldView {
@@ -582,22 +542,6 @@ constexpr int ACC_HALF = 4 * ACC_PLANE;
 template <typename T, int NF>
 __device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], const Sources& S,
                                                 const Pencil& p, int k0) {
-#if OCTOHYDRO_PROLOGUE_BATCH
-  T q[5][NF];
-#pragma unroll
-  for (int j = 0; j < 5; ++j) {
-    const Src src = pencil_src(p, k0 + j);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) q[j][f] = src_value<T>(S, f, src);
-  }
-#pragma unroll
-  for (int j = 0; j < 5; ++j)
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      T ul, ur;
-      ppm_push(st[f], q[j][f], j, ul, ur);
-    }
-#else
   // one position in flight ahead of the recurrences
   T cur[NF], nxt[NF];
   {
@@ -619,7 +563,6 @@ __device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], const Sources&
       cur[f] = nxt[f];
     }
   }
-#endif
 }
 
 // A steady stream step: feed the next value of every field and evaluate the
@@ -753,11 +696,6 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
 #pragma unroll
     for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(S, f, src);
   }
-#if OCTOHYDRO_U0_AHEAD
-  T u0next[NF];
-#pragma unroll
-  for (int f = 0; f < NF; ++f) u0next[f] = T(0);
-#endif
 #pragma unroll 1
   for (int kk = 5; kk < 10; ++kk) {
     const int k = k0 + kk;
@@ -771,40 +709,13 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
     }
     // U0 of the cell this step finishes: issued now, consumed after the
     // face evaluation, so the load's latency is covered by it
-    T u0v[NF], ukv[NF];
-    double accv[NF];
+    T u0v[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      u0v[f] = ukv[f] = T(0);
-      accv[f] = 0.0;
-    }
-#if OCTOHYDRO_U0_AHEAD
-    // U0 of this step's cell was loaded one step earlier
-#pragma unroll
-    for (int f = 0; f < NF; ++f) u0v[f] = u0next[f];
-    if (s.U0 && kk + 1 >= 6 && kk + 1 < 10) {
-      const uint32_t nb_b = (uint32_t)sizeof(T) * (leaf_at + (k + 1 - 6) * 64);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) u0next[f] = bload(T(), FieldView{U0, f * fs_b}, nb_b);
-    }
-#endif
-    if (kk >= 6) {
+    for (int f = 0; f < NF; ++f) u0v[f] = T(0);
+    if (kk >= 6 && s.U0) {
       const uint32_t cell_b = (uint32_t)sizeof(T) * (leaf_at + (k - 6) * 64);
-#if !OCTOHYDRO_U0_AHEAD
-      if (s.U0) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) u0v[f] = bload(T(), FieldView{U0, f * fs_b}, cell_b);
-      }
-#endif
-#if OCTOHYDRO_Z_RELOAD
-#pragma unroll
-      for (int f = 0; f < NF; ++f) ukv[f] = bload(T(), FieldView{Uk, f * fs_b}, cell_b);
-#endif
-#if OCTOHYDRO_ACC_EARLY
-      const int ai0 = (k - 6 - k0) * ACC_PLANE + y * ACC_PITCH + x;
-#pragma unroll
-      for (int f = 0; f < NF; ++f) accv[f] = acc[f * ACC_HALF + ai0];
-#endif
+      for (int f = 0; f < NF; ++f) u0v[f] = bload(T(), FieldView{U0, f * fs_b}, cell_b);
     }
     T H[NF];
     stream_step<T, NF>(ph, 2, st, qn, H, bad);
@@ -819,11 +730,7 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
         const double dx = 1.0 / (double)(SUB * li.blocks);
         const double rx = ((double)(SUB * li.ix + x) + 0.5) * dx - 0.5;
         const double ry = ((double)(SUB * li.iy + y) + 0.5) * dx - 0.5;
-#if OCTOHYDRO_Z_RELOAD
-        const double rho = (double)ukv[0], sx = (double)ukv[1], sy = (double)ukv[2];
-#else
         const double rho = (double)st[0].qy, sx = (double)st[1].qy, sy = (double)st[2].qy;
-#endif
         const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
         src[0] = tw * sy + rho * om2 * rx;
         src[1] = rho * om2 * ry - tw * sx;
@@ -831,17 +738,8 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
       }
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-#if OCTOHYDRO_ACC_EARLY
-        const double sum = accv[f] + ((double)H[f] - Hprev[f]);
-#else
         const double sum = acc[f * ACC_HALF + ai] + ((double)H[f] - Hprev[f]);
-#endif
-#if OCTOHYDRO_Z_RELOAD
-        const T uk = ukv[f];
-#else
-        const T uk = st[f].qy;
-#endif
-        finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, uk, u0v[f], sum,
+        finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, st[f].qy, u0v[f], sum,
                        rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
       }
     }
