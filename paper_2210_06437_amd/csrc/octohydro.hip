@@ -452,18 +452,24 @@ struct Sources {
   uint32_t uk_fs, rn_fs;
 };
 
-// The value a stream position takes in field f.  Where some lane of the
+// The values of a stream position in all NF fields.  Where some lane of the
 // wave reads a node copy, every lane loads from both arrays, one load with
 // an offset past the end (which reads 0 without a memory access), and keeps
-// its own: no divergent branch.
-template <typename T>
-__device__ __forceinline__ T src_value(const Sources& S, int f, Src s) {
+// its own: no divergent branch.  The test is made once per position, not
+// once per field.
+template <typename T, int NF>
+__device__ __forceinline__ void load_position(const Sources& S, const Src& s, T (&q)[NF]) {
   if (s.any_ref) {
-    const T a = bload(T(), FieldView{S.uk, f * S.uk_fs}, s.ouk);
-    const T b = bload(T(), FieldView{S.rn, f * S.rn_fs}, s.orn);
-    return s.ref ? b : a;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const T a = bload(T(), FieldView{S.uk, f * S.uk_fs}, s.ouk);
+      const T b = bload(T(), FieldView{S.rn, f * S.rn_fs}, s.orn);
+      q[f] = s.ref ? b : a;
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) q[f] = bload(T(), FieldView{S.uk, f * S.uk_fs}, s.o);
   }
-  return bload(T(), FieldView{S.uk, f * S.uk_fs}, s.o);
 }
 
 // Kurganov-Tadmor fluxes of the core fields at one face normal to axis d;
@@ -544,18 +550,10 @@ __device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], const Sources&
                                                 const Pencil& p, int k0) {
   // one position in flight ahead of the recurrences
   T cur[NF], nxt[NF];
-  {
-    const Src src = pencil_src(p, k0);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) cur[f] = src_value<T>(S, f, src);
-  }
+  load_position<T, NF>(S, pencil_src(p, k0), cur);
 #pragma unroll
   for (int j = 0; j < 5; ++j) {
-    if (j + 1 < 5) {
-      const Src src = pencil_src(p, k0 + j + 1);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) nxt[f] = src_value<T>(S, f, src);
-    }
+    if (j + 1 < 5) load_position<T, NF>(S, pencil_src(p, k0 + j + 1), nxt);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       T ul, ur;
@@ -623,21 +621,13 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
   }
   stream_prologue<T, NF>(st, S, p, 0);
   T qnext[NF];
-  {
-    const Src src = pencil_src(p, 5);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(S, f, src);
-  }
+  load_position<T, NF>(S, pencil_src(p, 5), qnext);
 #pragma unroll 1
   for (int k = 5; k < TW; ++k) {
     T qn[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) qn[f] = qnext[f];
-    if (k + 1 < TW) {
-      const Src src = pencil_src(p, k + 1);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(S, f, src);
-    }
+    if (k + 1 < TW) load_position<T, NF>(S, pencil_src(p, k + 1), qnext);
     T H[NF];
     stream_step<T, NF>(ph, d, st, qn, H, bad);
     if (g.reg && (k == 5 || k == TW - 1)) record_face<T, NF>(g, fn, k - 5, a, 4 * h + zz, H);
@@ -691,22 +681,14 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
   }
   stream_prologue<T, NF>(st, S, p, k0);
   T qnext[NF];
-  {
-    const Src src = pencil_src(p, k0 + 5);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(S, f, src);
-  }
+  load_position<T, NF>(S, pencil_src(p, k0 + 5), qnext);
 #pragma unroll 1
   for (int kk = 5; kk < 10; ++kk) {
     const int k = k0 + kk;
     T qn[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) qn[f] = qnext[f];
-    if (kk + 1 < 10) {
-      const Src src = pencil_src(p, k + 1);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) qnext[f] = src_value<T>(S, f, src);
-    }
+    if (kk + 1 < 10) load_position<T, NF>(S, pencil_src(p, k + 1), qnext);
     // U0 of the cell this step finishes: issued now, consumed after the
     // face evaluation, so the load's latency is covered by it
     T u0v[NF];
