@@ -53,7 +53,7 @@ extern "C" {
 #define HYDRO_E_TABLE (-2)        /* inconsistent neighbour table             */
 #define HYDRO_E_UNPHYSICAL (-3)   /* rho <= 0 or p <= 0 met at a face         */
 #define HYDRO_E_HIP (-4)          /* HIP runtime error (message has details)  */
-#define HYDRO_E_UNSUPPORTED (-5)  /* valid request this build does not serve  */
+#define HYDRO_E_UNSUPPORTED (-5)  /* valid request the library does not serve */
 
 /* element types */
 #define HYDRO_F64 0  /* binary64 storage and arithmetic                       */

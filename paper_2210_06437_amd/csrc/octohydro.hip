@@ -348,6 +348,7 @@ struct Pencil {
   uint32_t off, sd;
   u32x8 gofs;  // a vector value: selecting an entry never touches memory
   bool ref_lo, ref_hi;
+  bool any_lo, any_hi;  // some lane of the wave has ref_lo (ref_hi)
 };
 
 __device__ __forceinline__ uint32_t ghost_offset(const GridArgs& g, const LeafInfo& li, int kind,
@@ -376,6 +377,9 @@ __device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo&
   const int klo = fn.klo, ilo = fn.ilo, khi = fn.khi, ihi = fn.ihi;
   p.ref_lo = klo == HYDRO_SAME_REFINED;
   p.ref_hi = khi == HYDRO_SAME_REFINED;
+  // wave votes taken once per pencil, outside the streaming loops
+  p.any_lo = __any(p.ref_lo);
+  p.any_hi = __any(p.ref_hi);
 #pragma unroll
   for (int j = 0; j < 2 * GH; ++j) {
     const bool hi = j >= GH;
@@ -413,7 +417,7 @@ __device__ __forceinline__ Src pencil_src(const Pencil& p, int k) {
   s.o = k == 0 ? p.gofs[0] : k == 1 ? p.gofs[1] : k == 2 ? p.gofs[2]
       : k == 11 ? p.gofs[3] : k == 12 ? p.gofs[4] : p.gofs[5];
   s.ref = k < GH ? p.ref_lo : p.ref_hi;
-  s.any_ref = __any(s.ref);
+  s.any_ref = k < GH ? p.any_lo : p.any_hi;
   s.ouk = s.ref ? OFF_NONE : s.o;
   s.orn = s.ref ? s.o : OFF_NONE;
   return s;
@@ -541,6 +545,17 @@ __device__ __forceinline__ void finish_cell(const StepArgs& s, size_t fbase, uin
 // LDS accumulator of half a leaf (4 z-planes): field stride ACC_HALF.
 constexpr int ACC_HALF = 4 * ACC_PLANE;
 
+// Point after which lanes of a wave read LDS values that other lanes of the
+// same wave wrote.  One wave's LDS instructions execute in program order, so
+// the hardware needs no wait; the wavefront-scope fences (which emit no
+// instructions) keep the compiler from moving memory accesses across the
+// point, which the wave barrier alone does not.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // First five stream steps of all NF fields of a pencil (stream positions
 // k0..k0+4): they build the PPM recurrences up to the first complete cell;
 // no face is complete yet.  Unrolled, so each step does only the work its
@@ -591,10 +606,11 @@ __device__ __forceinline__ void stream_step(const Phys<T>& ph, int d, Ppm<T> (&s
 
 // Phase XY of half h: lanes 0-31 stream x-pencils, lanes 32-63 y-pencils of
 // the planes z in [4h, 4h+4).  Each cell receives dHx from one lane and dHy
-// from another; the lane that reaches the cell first (the x-lane on ties)
-// stores, the other adds after a wave-level ordering point.  A sum of two
-// binary64 values does not depend on their order, so the accumulator holds
-// exactly dHx + dHy.
+// from another, both as LDS atomic adds (ds_add_f64, which rounds as binary64
+// addition does) into an accumulator cleared to -0.0: -0.0 is the identity of
+// binary64 addition (it keeps the sign of a zero term) and a sum of two terms
+// does not depend on their order, so the accumulator holds exactly dHx + dHy
+// whichever lane gets there first, with no branch on the lane.
 template <typename T, int NF>
 __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
                                          const FaceNbr& fn, double* __restrict__ acc, int h,
@@ -612,6 +628,9 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
   const int acc_off = d == 0 ? zz * ACC_PLANE + a * ACC_PITCH : zz * ACC_PLANE + a;
   const int acc_step = d == 0 ? 1 : ACC_PITCH;
 
+  for (int j = lane; j < NF * ACC_HALF / 2; j += 64)
+    reinterpret_cast<double2*>(acc)[j] = make_double2(-0.0, -0.0);
+  wave_lds_sync();
   Ppm<T> st[NF];
   double Hprev[NF];
 #pragma unroll
@@ -633,20 +652,14 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
     if (g.reg && (k == 5 || k == TW - 1)) record_face<T, NF>(g, fn, k - 5, a, 4 * h + zz, H);
     if (k >= 6) {
       const int i = k - 6;  // interior cell along d: H now is its high face
-      const bool first = d == 0 ? i <= a : i < a;
       const int ai = acc_off + i * acc_step;
       double dH[NF];
 #pragma unroll
       for (int f = 0; f < NF; ++f) dH[f] = (double)H[f] - Hprev[f];
-      if (first) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) acc[f * ACC_HALF + ai] = dH[f];
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (!first) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) acc[f * ACC_HALF + ai] = acc[f * ACC_HALF + ai] + dH[f];
-      }
+      for (int f = 0; f < NF; ++f)
+        __hip_atomic_fetch_add(&acc[f * ACC_HALF + ai], dH[f], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) Hprev[f] = (double)H[f];
@@ -733,7 +746,7 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
 // W = register budget: W waves per SIMD (1: up to 512 VGPRs, 2: up to 256).
 template <typename T, int NF, int W>
 __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
-  __shared__ double acc[NF * ACC_HALF];
+  __shared__ __align__(16) double acc[NF * ACC_HALF];
   const GridArgs& g = s.g;
   int bid = blockIdx.x;
   if (s.remap) {
@@ -793,9 +806,9 @@ __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
 #pragma unroll 1
   for (int h = 0; h < 2; ++h) {
     phase_xy<T, NF>(s, ph, li, fxy, acc, h, lane, bad);
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
     phase_z<T, NF>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad);
-    __builtin_amdgcn_wave_barrier();
+    wave_lds_sync();
   }
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
 }
@@ -818,11 +831,7 @@ __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
 //   edges   = (H(0,-1) + H(0,1)) + (H(-1,0) + H(1,0)).
 //
 // Ghost cells come from tiles materialised by k_fill (all 26 regions: the
-// diagonal lines reach edge and corner ghosts).  One wave per leaf and one
-// phase per axis D; lane (u, v) owns the pencil along D through transverse
-// cell (u, v) and evaluates its 9 faces in turn.  The flux differences meet
-// in an LDS accumulator in the order ((x + y) + z); the z phase finishes the
-// cells exactly as k_step does.
+// diagonal lines reach edge and corner ghosts).
 // ---------------------------------------------------------------------------
 
 // One end of the PPM parabola of the cell at t along a line of tile stride s.
@@ -868,7 +877,10 @@ __device__ __forceinline__ T simpson9(const T (&h)[9]) {
 }
 
 // Flux of all fields through the face between tile cells tl and tl + stride
-// of D (Gt: field 0's tile of the leaf, field stride fsG).
+// of D (Gt: field 0's tile of the leaf, field stride fsG).  The core fields'
+// end values at all 9 points are read first (their loads are independent, so
+// many are in flight at once) and give the points' Kurganov-Tadmor fluxes,
+// velocities and signal speeds; each passive field then uses those speeds.
 template <typename T, int NF, int D>
 __device__ __forceinline__ void face_flux_3d(const Phys<T>& ph, const T* __restrict__ Gt,
                                              size_t fsG, int tl, T (&H)[NF], bool& bad) {
@@ -908,85 +920,39 @@ __device__ __forceinline__ void face_flux_3d(const Phys<T>& ph, const T* __restr
   }
 }
 
-// Phase D of the 3D step: lane (u, v) walks the 9 faces of its pencil.
-template <typename T, int NF, int D>
-__device__ __forceinline__ void phase3d(const StepArgs& s, const Phys<T>& ph,
-                                        const LeafInfo& li, const T* __restrict__ G,
-                                        double* __restrict__ acc, int lane, double dt,
-                                        double inv_dx, bool& bad) {
-  constexpr int U = D == 0 ? 1 : 0, V = D == 2 ? 1 : 2;
-  constexpr int ST[3] = {1, TW, TW * TW};
-  const GridArgs& g = s.g;
-  const int u = lane & 7, v = lane >> 3;
-  const size_t fsG = (size_t)g.n_leaves * TILE;
-  const size_t fs = (size_t)g.n_leaves * CELLS;
-  const T* __restrict__ Gt = G + (size_t)li.leaf * TILE;
-  const int t0 = (u + GH) * ST[U] + (v + GH) * ST[V];
+// Face-neighbour register slots of the faces normal to axis D.
+__device__ __forceinline__ FaceNbr face_slots_3d(const GridArgs& g, int leaf, int D) {
   FaceNbr fn;
   fn.klo = fn.ilo = fn.khi = fn.ihi = 0;
   fn.rlo = fn.rhi = fn.flo = fn.fhi = -1;
   if (g.reg) {
-    fn.rlo = g.face_slot[6 * li.leaf + 2 * D];
-    fn.rhi = g.face_slot[6 * li.leaf + 2 * D + 1];
-    fn.flo = g.fine_slot[6 * li.leaf + 2 * D];
-    fn.fhi = g.fine_slot[6 * li.leaf + 2 * D + 1];
+    fn.rlo = g.face_slot[6 * leaf + 2 * D];
+    fn.rhi = g.face_slot[6 * leaf + 2 * D + 1];
+    fn.flo = g.fine_slot[6 * leaf + 2 * D];
+    fn.fhi = g.fine_slot[6 * leaf + 2 * D + 1];
   }
-  double Hprev[NF];
-#pragma unroll
-  for (int f = 0; f < NF; ++f) Hprev[f] = 0.0;
-#pragma unroll 1
-  for (int k = GH - 1; k < GH + SUB; ++k) {
-    const int tl = t0 + k * ST[D];
-    T H[NF];
-    face_flux_3d<T, NF, D>(ph, Gt, fsG, tl, H, bad);
-    if (g.reg && (k == GH - 1 || k == GH + SUB - 1))
-      record_face<T, NF>(g, fn, k == GH - 1 ? 0 : 8, u, v, H);
-    if (k >= GH) {
-      const int i = k - GH;  // interior cell along D: H is its high face
-      int l[3];
-      l[D] = i;
-      l[U] = u;
-      l[V] = v;
-      const int cell = l[2] * 64 + l[1] * 8 + l[0];
-      if (D == 0) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) acc[f * CELLS + cell] = (double)H[f] - Hprev[f];
-      } else if (D == 1) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-          acc[f * CELLS + cell] = acc[f * CELLS + cell] + ((double)H[f] - Hprev[f]);
-      } else {
-        double src[4] = {0.0, 0.0, 0.0, 0.0};
-        const bool rot = g.omega != 0.0;
-        const T* __restrict__ ukc = Gt + tl;  // this cell's Uk (tile centre of cell k)
-        if (rot) {
-          const double dx = 1.0 / (double)(SUB * li.blocks);
-          const double rx = ((double)(SUB * li.ix + u) + 0.5) * dx - 0.5;
-          const double ry = ((double)(SUB * li.iy + v) + 0.5) * dx - 0.5;
-          const double rho = (double)ukc[0], sx = (double)ukc[fsG], sy = (double)ukc[2 * fsG];
-          const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
-          src[0] = tw * sy + rho * om2 * rx;
-          src[1] = rho * om2 * ry - tw * sx;
-          src[3] = om2 * (sx * rx + sy * ry);
-        }
-        const uint32_t at = (uint32_t)li.leaf * CELLS + cell;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const double sum = acc[f * CELLS + cell] + ((double)H[f] - Hprev[f]);
-          const T u0 = s.U0 ? static_cast<const T*>(s.U0)[(size_t)f * fs + at] : T(0);
-          finish_cell<T>(s, (size_t)f * fs, at, ukc[f * fsG], u0, sum, rot && f >= 1 && f <= 4,
-                         f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
-        }
-      }
-    }
-#pragma unroll
-    for (int f = 0; f < NF; ++f) Hprev[f] = (double)H[f];
-  }
+  return fn;
 }
 
+// Tile index of leaf cell (x, y, z); -1 and 8 name the ghost layers.
+__device__ __forceinline__ constexpr int tile_at(int x, int y, int z) {
+  return (x + GH) + (y + GH) * TW + (z + GH) * TW * TW;
+}
+
+// One wave per leaf sweeps the z-planes; lane (x, y) owns cell (x, y, z) of
+// the current plane.  A face's flux depends on no other face, so each plane
+// costs three face evaluations per lane, each of them a wave-wide load of
+// consecutive x-cells: the cell's low x-face, its low y-face and its high
+// z-face.  The high x-face (y-face) of a cell is the low face of lane x+1
+// (y+1), taken by a lane shuffle; for x = 7 (y = 7) it is face 8 of the row
+// (column), which a first pass evaluates for the whole leaf and keeps in LDS.
+// The low z-face is the high z-face of the plane before, kept in registers
+// (z-face 0 comes from the first pass).  The differences are summed
+// ((x + y) + z) in binary64 and the cell is finished as k_step does.
 template <typename T, int NF>
 __global__ void __launch_bounds__(64) k_step3d(StepArgs s, const T* __restrict__ G) {
-  __shared__ double acc[NF * CELLS];
+  __shared__ double hx8[NF * 64];  // x-face 8 of row (y, z), at z * 8 + y
+  __shared__ double hy8[NF * 64];  // y-face 8 of column (x, z), at z * 8 + x
   const GridArgs& g = s.g;
   const int leaf = s.leaf_base + blockIdx.x;
   if (leaf >= g.n_leaves) return;
@@ -1004,12 +970,88 @@ __global__ void __launch_bounds__(64) k_step3d(StepArgs s, const T* __restrict__
   ph.gamma = (T)g.gamma;
   ph.gm1 = (T)(g.gamma - 1.0);
   ph.eta1 = (T)g.eta1;
+  const size_t fsG = (size_t)g.n_leaves * TILE;
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const T* __restrict__ Gt = G + (size_t)leaf * TILE;
+  const FaceNbr fx = face_slots_3d(g, leaf, 0);
+  const FaceNbr fy = face_slots_3d(g, leaf, 1);
+  const FaceNbr fz = face_slots_3d(g, leaf, 2);
+  const int x = lane & 7, y = lane >> 3;
   bool bad = false;
-  phase3d<T, NF, 0>(s, ph, li, G, acc, lane, dt, inv_dx, bad);
-  __syncthreads();
-  phase3d<T, NF, 1>(s, ph, li, G, acc, lane, dt, inv_dx, bad);
-  __syncthreads();
-  phase3d<T, NF, 2>(s, ph, li, G, acc, lane, dt, inv_dx, bad);
+  const double dx = 1.0 / (double)(SUB * li.blocks);
+  const double rx = ((double)(SUB * li.ix + x) + 0.5) * dx - 0.5;
+  const double ry = ((double)(SUB * li.iy + y) + 0.5) * dx - 0.5;
+  double Hz[NF];
+  // z = -1 is the first pass: x-face 8 of row (a, b) and y-face 8 of column
+  // (a, b), (a, b) = (lane & 7, lane >> 3), into LDS, and z-face 0 of the
+  // lane's column into Hz.  Each later z evaluates the three faces of the
+  // lane's cell and finishes it.
+#pragma unroll 1
+  for (int z = -1; z < SUB; ++z) {
+    wave_lds_sync();  // the first pass's LDS values are read from z = 0 on
+    const bool first = z < 0;
+    T H[NF];
+    double sxy[NF];
+    face_flux_3d<T, NF, 0>(ph, Gt, fsG, first ? tile_at(SUB - 1, x, y) : tile_at(x - 1, y, z),
+                           H, bad);
+    if (first) {
+      if (g.reg) record_face<T, NF>(g, fx, SUB, x, y, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) hx8[f * 64 + lane] = (double)H[f];
+    } else {
+      if (g.reg && x == 0) record_face<T, NF>(g, fx, 0, y, z, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double lo = (double)H[f];
+        const double up = __shfl_down(lo, 1, 8);  // lane x+1: its low face
+        const double hi = x == SUB - 1 ? hx8[f * 64 + z * 8 + y] : up;
+        sxy[f] = hi - lo;
+      }
+    }
+    face_flux_3d<T, NF, 1>(ph, Gt, fsG, first ? tile_at(x, SUB - 1, y) : tile_at(x, y - 1, z),
+                           H, bad);
+    if (first) {
+      if (g.reg) record_face<T, NF>(g, fy, SUB, x, y, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) hy8[f * 64 + lane] = (double)H[f];
+    } else {
+      if (g.reg && y == 0) record_face<T, NF>(g, fy, 0, x, z, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double lo = (double)H[f];
+        const double up = __shfl_down(lo, 8, 64);  // lane y+1: its low face
+        const double hi = y == SUB - 1 ? hy8[f * 64 + z * 8 + x] : up;
+        sxy[f] = sxy[f] + (hi - lo);
+      }
+    }
+    face_flux_3d<T, NF, 2>(ph, Gt, fsG, tile_at(x, y, z), H, bad);
+    if (first) {
+      if (g.reg) record_face<T, NF>(g, fz, 0, x, y, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) Hz[f] = (double)H[f];
+      continue;
+    }
+    if (g.reg && z == SUB - 1) record_face<T, NF>(g, fz, SUB, x, y, H);
+    const T* __restrict__ ukc = Gt + tile_at(x, y, z);  // the cell's Uk
+    double src[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool rot = g.omega != 0.0;
+    if (rot) {
+      const double rho = (double)ukc[0], sx = (double)ukc[fsG], sy = (double)ukc[2 * fsG];
+      const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+      src[0] = tw * sy + rho * om2 * rx;
+      src[1] = rho * om2 * ry - tw * sx;
+      src[3] = om2 * (sx * rx + sy * ry);
+    }
+    const uint32_t at = (uint32_t)leaf * CELLS + z * 64 + lane;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double sum = sxy[f] + ((double)H[f] - Hz[f]);
+      Hz[f] = (double)H[f];
+      const T u0 = s.U0 ? static_cast<const T*>(s.U0)[(size_t)f * fs + at] : T(0);
+      finish_cell<T>(s, (size_t)f * fs, at, ukc[f * fsG], u0, sum, rot && f >= 1 && f <= 4,
+                     f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+    }
+  }
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
 }
 
