@@ -351,13 +351,14 @@ struct Pencil {
   bool any_lo, any_hi;  // some lane of the wave has ref_lo (ref_hi)
 };
 
+// cd = the leaf's block coordinate along d.
 __device__ __forceinline__ uint32_t ghost_offset(const GridArgs& g, const LeafInfo& li, int kind,
-                                                 int id, int side, int d, int lx, int ly,
+                                                 int id, int side, int d, int cd, int lx, int ly,
                                                  int lz) {
   if (kind == HYDRO_SAME_LEAF) return id * CELLS + lz * 64 + ly * 8 + lx;
   if (kind == HYDRO_COARSER_LEAF) {
     // the neighbour block along d, wrapped; transverse blocks are the leaf's
-    const int nb = wrap((d == 0 ? li.ix : (d == 1 ? li.iy : li.iz)) + side, li.blocks);
+    const int nb = wrap(cd + side, li.blocks);
     const int bx = d == 0 ? nb : li.ix, by = d == 1 ? nb : li.iy, bz = d == 2 ? nb : li.iz;
     return id * CELLS + (4 * (bz & 1) + (lz >> 1)) * 64 + (4 * (by & 1) + (ly >> 1)) * 8 +
            (4 * (bx & 1) + (lx >> 1));
@@ -380,6 +381,10 @@ __device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo&
   // wave votes taken once per pencil, outside the streaming loops
   p.any_lo = __any(p.ref_lo);
   p.any_hi = __any(p.ref_hi);
+  // the block coordinate along d (d may differ between lanes), as arithmetic
+  // on values: a select between the LeafInfo fields became an indexed load
+  // from a scratch copy of it, with a full memory wait per ghost position
+  const int cd = (d == 0) * li.ix + (d == 1) * li.iy + (d == 2) * li.iz;
 #pragma unroll
   for (int j = 0; j < 2 * GH; ++j) {
     const bool hi = j >= GH;
@@ -388,7 +393,7 @@ __device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo&
     const int ly = d == 0 ? a : (d == 1 ? l : b);
     const int lz = d == 2 ? l : b;
     p.gofs[j] =
-        W * ghost_offset(g, li, hi ? khi : klo, hi ? ihi : ilo, hi ? 1 : -1, d, lx, ly, lz);
+        W * ghost_offset(g, li, hi ? khi : klo, hi ? ihi : ilo, hi ? 1 : -1, d, cd, lx, ly, lz);
   }
   return p;
 }
