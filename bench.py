@@ -216,13 +216,19 @@ def cpu_baseline(w, n_sample_leaves=65535):
 
 
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "k_step_turbulence65k_f64_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2210_06437_amd", "csrc", "octohydro.hip")
+KERNEL_DIR = os.path.join(ROOT, "paper_2210_06437_amd", "csrc")
 
 
 def source_digest() -> str:
+    """sha256 over the library's HIP sources and headers, in name order."""
+    import glob
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(KERNEL_DIR, "*.hip")) +
+                       glob.glob(os.path.join(KERNEL_DIR, "*.h"))):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic():

@@ -1,0 +1,11 @@
+// Instantiations of the 3D step kernel k_step3d, binary32 storage, 15 to 16
+// fields: one of the units its instantiations are spread over so that they
+// compile in parallel.
+#include "octohydro_kernels.h"
+
+namespace octohydro {
+
+template hipError_t launch_step3d_one<float, 15>(const StepArgs&, int, const float*, hipStream_t);
+template hipError_t launch_step3d_one<float, 16>(const StepArgs&, int, const float*, hipStream_t);
+
+}  // namespace octohydro

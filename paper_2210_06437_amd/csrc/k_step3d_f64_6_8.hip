@@ -1,0 +1,12 @@
+// Instantiations of the 3D step kernel k_step3d, binary64, 6 to 8
+// fields: one of the units its instantiations are spread over so that they
+// compile in parallel.
+#include "octohydro_kernels.h"
+
+namespace octohydro {
+
+template hipError_t launch_step3d_one<double, 6>(const StepArgs&, int, const double*, hipStream_t);
+template hipError_t launch_step3d_one<double, 7>(const StepArgs&, int, const double*, hipStream_t);
+template hipError_t launch_step3d_one<double, 8>(const StepArgs&, int, const double*, hipStream_t);
+
+}  // namespace octohydro

@@ -1,0 +1,1108 @@
+// Device code of liboctohydro shared by its translation units: constants,
+// argument structs, the method's device functions, and the kernel templates
+// with their launchers.  Each kernel is instantiated only in the translation
+// unit that launches it (octohydro.hip: ghost fill, restriction, CFL, totals,
+// flux correction; k_step_f64.hip and k_step_f32.hip: the fused substep per
+// precision; k_step3d.hip: the 3D step), so the units compile in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "octohydro.h"
+
+namespace octohydro {
+
+constexpr int SUB = 8;
+constexpr int GH = 3;
+constexpr int TW = SUB + 2 * GH;  // 14
+constexpr int CELLS = SUB * SUB * SUB;
+constexpr int TILE = TW * TW * TW;
+constexpr int NF_CORE = 6;  // rho, sx, sy, sz, E, tau
+constexpr int ACC_PITCH = 9;  // LDS row pitch (doubles) of the accumulator
+constexpr int ACC_PLANE = SUB * ACC_PITCH;
+constexpr int ACC_FIELD = SUB * ACC_PLANE;
+// A buffer offset past the end of every array the kernels address (array
+// sizes are bounded below it on the host): a buffer load there returns 0
+// without touching memory.
+constexpr uint32_t OFF_NONE = 0xFFFFF000u;
+
+struct GridArgs {
+  int32_t n_leaves;
+  int32_t n_nodes;
+  int32_t nf;
+  int32_t base;
+  const int32_t* coord;
+  const int32_t* nbr;
+  const uint8_t* kind;
+  const int32_t* children;
+  int32_t* status;
+  double gamma;
+  double eta1;
+  // flux register (NULL: no coarse-fine flux correction)
+  const int32_t* face_slot;
+  const int32_t* fine_slot;
+  const int32_t* slot_leaf;
+  double* reg;
+  double omega;  // rotating-frame angular velocity (0: no sources)
+  void* rstate;  // restricted copies of the refined nodes [nf][n_nodes][512]
+};
+
+// Values per register slot and field: 64 coarse face fluxes, then the 16x16
+// fine face fluxes that cover the same face.
+constexpr int REG_COARSE = 64;
+constexpr int REG_STRIDE = 64 + 256;
+
+__device__ __forceinline__ int wrap(int a, int m) {
+  a = a < 0 ? a + m : a;
+  return a >= m ? a - m : a;
+}
+
+// ---------------------------------------------------------------------------
+// Ghost values (Sec. VI): same-level copy, injection from a coarser leaf, or
+// restriction (mean of the 8 covering cells) from a refined neighbour.
+// ---------------------------------------------------------------------------
+
+// Value of the neighbour-side cell with local coordinates l[3] in [0,8) of
+// the neighbour block in direction r[3] (each in {-1,0,1}) of `leaf`.
+template <typename T>
+__device__ __forceinline__ T neighbour_value(const GridArgs& g, const T* __restrict__ Uf, int leaf,
+                                             const int (&ic)[3], int blocks, int kind, int id,
+                                             const int (&r)[3], const int (&l)[3]) {
+  if (kind == HYDRO_SAME_LEAF) {
+    return Uf[(size_t)id * CELLS + l[2] * 64 + l[1] * 8 + l[0]];
+  }
+  if (kind == HYDRO_COARSER_LEAF) {
+    int c[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int nb = wrap(ic[k] + r[k], blocks);
+      c[k] = 4 * (nb & 1) + (l[k] >> 1);
+    }
+    return Uf[(size_t)id * CELLS + c[2] * 64 + c[1] * 8 + c[0]];
+  }
+  // refined neighbour: child (l >> 2) on each axis, fine cells (2l + bit) & 7
+  const int child = g.children[8 * id + (l[2] >> 2) * 4 + (l[1] >> 2) * 2 + (l[0] >> 2)];
+  const T* __restrict__ P = Uf + (size_t)child * CELLS;
+  const int fx0 = (2 * l[0]) & 7, fy0 = (2 * l[1]) & 7, fz0 = (2 * l[2]) & 7;
+  const T v000 = P[fz0 * 64 + fy0 * 8 + fx0];
+  const T v100 = P[fz0 * 64 + fy0 * 8 + fx0 + 1];
+  const T v010 = P[fz0 * 64 + (fy0 + 1) * 8 + fx0];
+  const T v110 = P[fz0 * 64 + (fy0 + 1) * 8 + fx0 + 1];
+  const T v001 = P[(fz0 + 1) * 64 + fy0 * 8 + fx0];
+  const T v101 = P[(fz0 + 1) * 64 + fy0 * 8 + fx0 + 1];
+  const T v011 = P[(fz0 + 1) * 64 + (fy0 + 1) * 8 + fx0];
+  const T v111 = P[(fz0 + 1) * 64 + (fy0 + 1) * 8 + fx0 + 1];
+  return T(0.125) * (((v000 + v100) + (v010 + v110)) + ((v001 + v101) + (v011 + v111)));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_fill(GridArgs g, const T* __restrict__ U, T* __restrict__ G, int64_t total) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(idx % TILE);
+    const int64_t fl = idx / TILE;
+    const int leaf = (int)(fl % g.n_leaves);
+    const int f = (int)(fl / g.n_leaves);
+    const int tp[3] = {t % TW, (t / TW) % TW, t / (TW * TW)};
+    int r[3], l[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      r[k] = tp[k] < GH ? -1 : (tp[k] >= GH + SUB ? 1 : 0);
+      l[k] = tp[k] - GH - SUB * r[k];
+    }
+    const T* __restrict__ Uf = U + (size_t)f * g.n_leaves * CELLS;
+    const int slot = (r[2] + 1) * 9 + (r[1] + 1) * 3 + (r[0] + 1);
+    T v;
+    if (slot == 13) {
+      v = Uf[(size_t)leaf * CELLS + l[2] * 64 + l[1] * 8 + l[0]];
+    } else {
+      const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
+      const int ic[3] = {c4.y, c4.z, c4.w};
+      const int blocks = g.base << c4.x;
+      v = neighbour_value<T>(g, Uf, leaf, ic, blocks, g.kind[27 * leaf + slot],
+                             g.nbr[27 * leaf + slot], r, l);
+    }
+    G[idx] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Restricted copies of the refined nodes (the coarse side of a coarse-fine
+// face, Sec. VI): coarse cell (x, y, z) of node n is the mean of the 8 cells
+// of child (x>>2, y>>2, z>>2) that cover it, summed in the same fixed order as
+// the ghost fill.  Cells of a missing child are never read; they are set to 0.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  typedef double2 type;
+};
+template <>
+struct Pair<float> {
+  typedef float2 type;
+};
+
+// Workgroup (node, field) of 512 threads, thread = coarse cell; the two x
+// neighbours of each fine pair are read as one aligned 2-element load.
+template <typename T>
+__global__ void __launch_bounds__(512)
+    k_restrict(GridArgs g, const T* __restrict__ U, T* __restrict__ R) {
+  typedef typename Pair<T>::type P;
+  const int node = blockIdx.x, f = blockIdx.y, c = threadIdx.x;
+  const int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+  const int child = g.children[8 * node + (z >> 2) * 4 + (y >> 2) * 2 + (x >> 2)];
+  T v = T(0);
+  if (child >= 0) {
+    const T* u = U + (size_t)f * g.n_leaves * CELLS + (size_t)child * CELLS +
+                 ((2 * z) & 7) * 64 + ((2 * y) & 7) * 8 + ((2 * x) & 7);
+    const P a = *reinterpret_cast<const P*>(u), b = *reinterpret_cast<const P*>(u + 8),
+            d = *reinterpret_cast<const P*>(u + 64), e = *reinterpret_cast<const P*>(u + 72);
+    v = T(0.125) * (((a.x + a.y) + (b.x + b.y)) + ((d.x + d.y) + (e.x + e.y)));
+  }
+  R[((size_t)f * g.n_nodes + node) * CELLS + c] = v;
+}
+
+// ---------------------------------------------------------------------------
+// PPM (Colella & Woodward 1984) as a streaming recurrence along a pencil.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct Ppm {
+  T qa, qb;   // q[k-2], q[k-1]
+  T qz, qy;   // q[k-3], q[k-4]
+  T dmA;      // limited slope of cell k-2
+  T qfA;      // interface value between cells k-3 and k-2
+  T Rprev;    // right face value of cell k-3
+};
+
+// Limited slope of cell j from q[j-1], q[j], q[j+1].
+template <typename T>
+__device__ __forceinline__ T limited_slope(T qm, T q0, T qp) {
+  const T dq = T(0.5) * (qp - qm);
+  const T dl = q0 - qm;
+  const T dr = qp - q0;
+  // min(2|dl|, 2|dr|) evaluated as 2 min(|dl|, |dr|): scaling by 2 is exact
+  // and monotone, so both give the same bits
+  const T lim = fmin(fabs(dq), T(2) * fmin(fabs(dl), fabs(dr)));
+  return (dl * dr > T(0)) ? copysign(lim, dq) : T(0);
+}
+
+// Monotonised parabola of a cell with centre value c and face values l, r.
+template <typename T>
+__device__ __forceinline__ void monotonise(T c, T& l, T& r) {
+  const T dlr = r - l;
+  const T a6 = T(6) * (c - T(0.5) * (l + r));
+  const T lo = T(3) * c - T(2) * r;
+  const T ro = T(3) * c - T(2) * l;
+  const bool flat = (r - c) * (c - l) <= T(0);
+  const bool fix_l = dlr * a6 > dlr * dlr;
+  const bool fix_r = -(dlr * dlr) > dlr * a6;
+  // fix_l and fix_r exclude each other (dlr^2 >= 0, and a NaN makes both
+  // false), so the right value needs no test of fix_l
+  const T nl = flat ? c : (fix_l ? lo : l);
+  const T nr = flat ? c : (fix_r ? ro : r);
+  l = nl;
+  r = nr;
+}
+
+// Feed the k-th value of a pencil stream; when k >= 5, returns the face
+// states of the face between stream cells k-3 and k-2 in (UL, UR).  k is a
+// compile-time constant after unrolling.
+template <typename T>
+__device__ __forceinline__ void ppm_push(Ppm<T>& s, T qn, int k, T& UL, T& UR) {
+  T dm_new = T(0), qf_new = T(0), Lc = T(0), Rc = T(0);
+  if (k >= 2) dm_new = limited_slope(s.qa, s.qb, qn);
+  if (k >= 3) qf_new = T(0.5) * (s.qa + s.qb) - (dm_new - s.dmA) * T(1.0 / 6.0);
+  if (k >= 4) {
+    Lc = s.qfA;
+    Rc = qf_new;
+    monotonise(s.qa, Lc, Rc);
+  }
+  if (k >= 5) {
+    UL = s.Rprev;
+    UR = Lc;
+  }
+  s.Rprev = Rc;
+  s.qfA = qf_new;
+  s.dmA = dm_new;
+  s.qy = s.qz;
+  s.qz = s.qa;
+  s.qa = s.qb;
+  s.qb = qn;
+}
+
+// ---------------------------------------------------------------------------
+// EOS and Kurganov-Tadmor flux
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct Phys {
+  T gamma, gm1, eta1;
+};
+
+// Internal energy density from the entropy tracer, tau^gamma (dual-energy
+// switch).  Kept out of line: the branch is rare and the inlined pow would
+// hold registers in the hot loop.
+static __device__ __noinline__ double tau_energy(double tau, double gamma) { return pow(tau, gamma); }
+static __device__ __noinline__ float tau_energy(float tau, float gamma) { return powf(tau, gamma); }
+
+// rinv = 1/rho, p, c for conserved state (rho, sx, sy, sz, E, tau).
+template <typename T>
+__device__ __forceinline__ bool eos(const Phys<T>& ph, T rho, T sx, T sy, T sz, T E, T tau,
+                                    T& rinv, T& p, T& c) {
+  rinv = T(1) / rho;
+  const T ss = (sx * sx + sy * sy) + sz * sz;
+  T ei = E - T(0.5) * ss * rinv;
+  if (ei < ph.eta1 * E) ei = tau_energy(tau, ph.gamma);
+  p = ph.gm1 * ei;
+  c = sqrt(ph.gamma * p * rinv);
+  return !(rho > T(0)) || !(p > T(0));
+}
+
+// ---------------------------------------------------------------------------
+// Fused substep kernel
+// ---------------------------------------------------------------------------
+
+struct StepArgs {
+  GridArgs g;
+  const void* U0;
+  const void* Uk;
+  void* Uout;
+  const double* dt;
+  double beta;
+  int32_t leaf_base;  // first leaf (per-leaf launches); 0 for the batch
+  int32_t remap;      // 1: spread contiguous leaf ranges over the 8 XCDs
+};
+
+// Per-leaf constants.  Neighbour kinds and ids of the six face neighbours are
+// handed to the phases as plain values (the phase picks its axis once), so
+// no per-lane choice is ever made by indexing memory.
+struct LeafInfo {
+  int leaf, blocks;
+  int ix, iy, iz;
+};
+
+// Face neighbour (kind, id) of a pencil axis, low and high side.
+struct FaceNbr {
+  int klo, ilo, khi, ihi;
+  int rlo, rhi;  // coarse register slot of the low / high face, or -1
+  int flo, fhi;  // fine register entry (slot << 2 | quadrant), or -1
+};
+
+// Record the fluxes H (all fields) through face `face` (0 = low, 8 = high
+// face of the leaf) of a pencil at transverse position (u, v) of that face.
+template <typename T, int NF>
+__device__ __forceinline__ void record_face(const GridArgs& g, const FaceNbr& fn, int face, int u,
+                                            int v, const T (&H)[NF]) {
+  const int cs = face == 0 ? fn.rlo : fn.rhi;
+  const int fe = face == 0 ? fn.flo : fn.fhi;
+  if (cs >= 0) {
+    double* r = g.reg + (size_t)cs * NF * REG_STRIDE + u + 8 * v;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) r[f * REG_STRIDE] = (double)H[f];
+  }
+  if (fe >= 0) {
+    const int q = fe & 3;
+    double* r = g.reg + (size_t)(fe >> 2) * NF * REG_STRIDE + REG_COARSE +
+                (8 * (q & 1) + u) + 16 * (8 * (q >> 1) + v);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) r[f * REG_STRIDE] = (double)H[f];
+  }
+}
+
+// A lane's pencil along axis d through transverse cell (a, b): where each of
+// its 14 stream values comes from, as byte offsets into a field array.
+// Interior value k sits at off + (k-3) sd; each ghost value k in
+// {0,1,2,11,12,13} comes from gofs[] -- a same-level cell or the covering
+// coarse cell (injection) of the state, or, on a refined side (ref_lo /
+// ref_hi), a cell of the refined node's restricted copy.  The sources are the
+// same for every field, so they are worked out once per pencil.
+typedef uint32_t u32x8 __attribute__((ext_vector_type(8)));
+
+struct Pencil {
+  uint32_t off, sd;
+  u32x8 gofs;  // a vector value: selecting an entry never touches memory
+  bool ref_lo, ref_hi;
+  bool any_lo, any_hi;  // some lane of the wave has ref_lo (ref_hi)
+};
+
+// cd = the leaf's block coordinate along d.
+__device__ __forceinline__ uint32_t ghost_offset(const GridArgs& g, const LeafInfo& li, int kind,
+                                                 int id, int side, int d, int cd, int lx, int ly,
+                                                 int lz) {
+  if (kind == HYDRO_SAME_LEAF) return id * CELLS + lz * 64 + ly * 8 + lx;
+  if (kind == HYDRO_COARSER_LEAF) {
+    // the neighbour block along d, wrapped; transverse blocks are the leaf's
+    const int nb = wrap(cd + side, li.blocks);
+    const int bx = d == 0 ? nb : li.ix, by = d == 1 ? nb : li.iy, bz = d == 2 ? nb : li.iz;
+    return id * CELLS + (4 * (bz & 1) + (lz >> 1)) * 64 + (4 * (by & 1) + (ly >> 1)) * 8 +
+           (4 * (bx & 1) + (lx >> 1));
+  }
+  // refined neighbour: the coarse cell of the node's restricted copy
+  return id * CELLS + lz * 64 + ly * 8 + lx;
+}
+
+template <typename T>
+__device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo& li, int d, int a,
+                                              int b, const FaceNbr& fn) {
+  Pencil p;
+  constexpr uint32_t W = sizeof(T);
+  // d = 0: (x, a=y, b=z); d = 1: (a=x, y, b=z); d = 2: (a=x, b=y, z)
+  p.off = W * (li.leaf * CELLS + (d == 0 ? b * 64 + a * 8 : (d == 1 ? b * 64 + a : b * 8 + a)));
+  p.sd = W * (d == 0 ? 1 : (d == 1 ? 8 : 64));
+  const int klo = fn.klo, ilo = fn.ilo, khi = fn.khi, ihi = fn.ihi;
+  p.ref_lo = klo == HYDRO_SAME_REFINED;
+  p.ref_hi = khi == HYDRO_SAME_REFINED;
+  // wave votes taken once per pencil, outside the streaming loops
+  p.any_lo = __any(p.ref_lo);
+  p.any_hi = __any(p.ref_hi);
+  // the block coordinate along d (d may differ between lanes), as arithmetic
+  // on values: a select between the LeafInfo fields became an indexed load
+  // from a scratch copy of it, with a full memory wait per ghost position
+  const int cd = (d == 0) * li.ix + (d == 1) * li.iy + (d == 2) * li.iz;
+#pragma unroll
+  for (int j = 0; j < 2 * GH; ++j) {
+    const bool hi = j >= GH;
+    const int l = hi ? j - GH : j + SUB - GH;  // cell along d inside the neighbour block
+    const int lx = d == 0 ? l : a;
+    const int ly = d == 0 ? a : (d == 1 ? l : b);
+    const int lz = d == 2 ? l : b;
+    p.gofs[j] =
+        W * ghost_offset(g, li, hi ? khi : klo, hi ? ihi : ilo, hi ? 1 : -1, d, cd, lx, ly, lz);
+  }
+  return p;
+}
+
+// Where stream position k (0..13) of a pencil comes from: a byte offset
+// into a field array and whether it is a refined ghost (mean of 8 cells).
+// Worked out once per stream step and shared by every field; for a step
+// index known only at run time the ghost offset is picked by a select chain
+// over the six values.
+struct Src {
+  uint32_t o;    // offset of the value in its array
+  uint32_t ouk;  // offset into the stage input, OFF_NONE on a refined side
+  uint32_t orn;  // offset into the node copies, OFF_NONE elsewhere
+  bool ref;      // this lane's value comes from a node copy
+  bool any_ref;  // some lane of the wave reads a node copy (wave-uniform)
+};
+
+__device__ __forceinline__ Src pencil_src(const Pencil& p, int k) {
+  Src s;
+  if (k >= GH && k < GH + SUB) {
+    s.o = s.ouk = p.off + (uint32_t)(k - GH) * p.sd;
+    s.orn = OFF_NONE;
+    s.ref = s.any_ref = false;
+    return s;
+  }
+  s.o = k == 0 ? p.gofs[0] : k == 1 ? p.gofs[1] : k == 2 ? p.gofs[2]
+      : k == 11 ? p.gofs[3] : k == 12 ? p.gofs[4] : p.gofs[5];
+  s.ref = k < GH ? p.ref_lo : p.ref_hi;
+  s.any_ref = k < GH ? p.any_lo : p.any_hi;
+  s.ouk = s.ref ? OFF_NONE : s.o;
+  s.orn = s.ref ? s.o : OFF_NONE;
+  return s;
+}
+
+// Buffer view of a state array: a 128-bit resource (base address, size)
+// held in scalar registers.  A load names the field by a scalar byte offset
+// (f times the field stride) and the cell by a 32-bit lane byte offset plus
+// a small immediate, so no 64-bit per-lane address is ever formed.  The
+// whole array must stay below 4 GiB (checked on the host).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int RSRC_WORD3 = 0x00020000;  // raw dword data format (gfx9 family)
+
+__device__ __forceinline__ Rsrc state_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, RSRC_WORD3);
+}
+
+// Field view: the array's resource and the field's scalar byte offset.
+struct FieldView {
+  Rsrc r;
+  uint32_t fo;
+};
+
+__device__ __forceinline__ double bload(double, const FieldView& v, uint32_t o) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(v.r, (int)o, (int)v.fo, 0));
+}
+__device__ __forceinline__ float bload(float, const FieldView& v, uint32_t o) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v.r, (int)o, (int)v.fo, 0));
+}
+
+// The two arrays stream values come from: the stage input (all interior and
+// same-level or coarser ghosts) and the restricted node copies (ghosts on a
+// refined side), each with its field stride in bytes.
+struct Sources {
+  Rsrc uk, rn;
+  uint32_t uk_fs, rn_fs;
+};
+
+// The values of a stream position in all NF fields.  Where some lane of the
+// wave reads a node copy, every lane loads from both arrays, one load with
+// an offset past the end (which reads 0 without a memory access), and keeps
+// its own: no divergent branch.  The test is made once per position, not
+// once per field.
+template <typename T, int NF>
+__device__ __forceinline__ void load_position(const Sources& S, const Src& s, T (&q)[NF]) {
+  if (s.any_ref) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const T a = bload(T(), FieldView{S.uk, f * S.uk_fs}, s.ouk);
+      const T b = bload(T(), FieldView{S.rn, f * S.rn_fs}, s.orn);
+      q[f] = s.ref ? b : a;
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) q[f] = bload(T(), FieldView{S.uk, f * S.uk_fs}, s.o);
+  }
+}
+
+// Kurganov-Tadmor fluxes of the core fields at one face normal to axis d;
+// also returns the face's normal velocities and half the signal speed for
+// the passive species.
+template <typename T>
+__device__ __forceinline__ void core_flux(const Phys<T>& ph, int d, const T (&UL)[NF_CORE],
+                                          const T (&UR)[NF_CORE], T (&H)[NF_CORE], T& vL, T& vR,
+                                          T& ha, bool& bad) {
+  T riL, pL, cL, riR, pR, cR;
+  bad |= eos(ph, UL[0], UL[1], UL[2], UL[3], UL[4], UL[5], riL, pL, cL);
+  bad |= eos(ph, UR[0], UR[1], UR[2], UR[3], UR[4], UR[5], riR, pR, cR);
+  const T snL = d == 0 ? UL[1] : (d == 1 ? UL[2] : UL[3]);
+  const T snR = d == 0 ? UR[1] : (d == 1 ? UR[2] : UR[3]);
+  vL = snL * riL;
+  vR = snR * riR;
+  ha = T(0.5) * fmax(fabs(vL) + cL, fabs(vR) + cR);
+  T FL[NF_CORE], FR[NF_CORE];
+  FL[0] = snL;
+  FR[0] = snR;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const T fl = UL[1 + m] * vL;
+    const T fr = UR[1 + m] * vR;
+    FL[1 + m] = m == d ? fl + pL : fl;
+    FR[1 + m] = m == d ? fr + pR : fr;
+  }
+  FL[4] = (UL[4] + pL) * vL;
+  FR[4] = (UR[4] + pR) * vR;
+  FL[5] = UL[5] * vL;
+  FR[5] = UR[5] * vR;
+#pragma unroll
+  for (int f = 0; f < NF_CORE; ++f) H[f] = T(0.5) * (FL[f] + FR[f]) - ha * (UR[f] - UL[f]);
+}
+
+// Stage combination of one cell: t = Uk + dt L with L = -sum * inv_dx, then
+// t (first stage) or U0 + beta (t - U0); u0 is the cell's U0 value, loaded
+// by the caller ahead of time.
+template <typename T>
+__device__ __forceinline__ void finish_cell(const StepArgs& s, size_t fbase, uint32_t cell, T uk,
+                                            T u0, double sum, bool has_src, double src,
+                                            double dt, double inv_dx) {
+  double lrate = -sum * inv_dx;
+  if (has_src) lrate = lrate + src;
+  const double t = (double)uk + dt * lrate;
+  double out;
+  if (s.U0) {
+    const double u = (double)u0;
+    out = u + s.beta * (t - u);
+  } else {
+    out = t;
+  }
+  // the result is not read again by this kernel: keep it out of the caches
+  __builtin_nontemporal_store((T)out, static_cast<T*>(s.Uout) + fbase + cell);
+}
+
+// Scheduling fence between the per-field reconstructions of a stream step:
+// the fields are then evaluated one after another instead of interleaved,
+// which keeps fewer temporaries alive (measured: FP32 -7 %, FP64 neutral).
+#ifndef OCTOHYDRO_FENCE_FIELDS
+#define OCTOHYDRO_FENCE_FIELDS 1
+#endif
+#if OCTOHYDRO_FENCE_FIELDS
+#define OCTOHYDRO_FENCE() __builtin_amdgcn_sched_barrier(0)
+#else
+#define OCTOHYDRO_FENCE() ((void)0)
+#endif
+
+// LDS accumulator of half a leaf (4 z-planes): field stride ACC_HALF.
+constexpr int ACC_HALF = 4 * ACC_PLANE;
+
+// Point after which lanes of a wave read LDS values that other lanes of the
+// same wave wrote.  One wave's LDS instructions execute in program order, so
+// the hardware needs no wait; the wavefront-scope fences (which emit no
+// instructions) keep the compiler from moving memory accesses across the
+// point, which the wave barrier alone does not.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// First five stream steps of all NF fields of a pencil (stream positions
+// k0..k0+4): they build the PPM recurrences up to the first complete cell;
+// no face is complete yet.  Unrolled, so each step does only the work its
+// stencil allows.
+template <typename T, int NF>
+__device__ __forceinline__ void stream_prologue(Ppm<T> (&st)[NF], const Sources& S,
+                                                const Pencil& p, int k0) {
+  // one position in flight ahead of the recurrences
+  T cur[NF], nxt[NF];
+  load_position<T, NF>(S, pencil_src(p, k0), cur);
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    if (j + 1 < 5) load_position<T, NF>(S, pencil_src(p, k0 + j + 1), nxt);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      T ul, ur;
+      ppm_push(st[f], cur[f], j, ul, ur);
+      cur[f] = nxt[f];
+    }
+  }
+}
+
+// A steady stream step: feed the next value of every field and evaluate the
+// face between stream cells k-3 and k-2 (fluxes in H).  The core fields are
+// reconstructed first and give the face's velocities and signal speed; each
+// passive species is then reconstructed and fluxed on its own, so only one
+// species' face states are ever held at a time.
+template <typename T, int NF>
+__device__ __forceinline__ void stream_step(const Phys<T>& ph, int d, Ppm<T> (&st)[NF],
+                                            const T (&qn)[NF], T (&H)[NF], bool& bad) {
+  T core_L[NF_CORE], core_R[NF_CORE], Hc[NF_CORE], vL, vR, ha;
+#pragma unroll
+  for (int f = 0; f < NF_CORE; ++f) {
+    ppm_push(st[f], qn[f], 5, core_L[f], core_R[f]);
+    OCTOHYDRO_FENCE();
+  }
+  core_flux(ph, d, core_L, core_R, Hc, vL, vR, ha, bad);
+#pragma unroll
+  for (int f = 0; f < NF_CORE; ++f) H[f] = Hc[f];
+#pragma unroll
+  for (int f = NF_CORE; f < NF; ++f) {
+    OCTOHYDRO_FENCE();
+    T ul, ur;
+    ppm_push(st[f], qn[f], 5, ul, ur);
+    H[f] = T(0.5) * (ul * vL + ur * vR) - ha * (ur - ul);
+  }
+}
+
+// Phase XY of half h: lanes 0-31 stream x-pencils, lanes 32-63 y-pencils of
+// the planes z in [4h, 4h+4).  Each cell receives dHx from one lane and dHy
+// from another, both as LDS atomic adds (ds_add_f64, which rounds as binary64
+// addition does) into an accumulator cleared to -0.0: -0.0 is the identity of
+// binary64 addition (it keeps the sign of a zero term) and a sum of two terms
+// does not depend on their order, so the accumulator holds exactly dHx + dHy
+// whichever lane gets there first, with no branch on the lane.
+template <typename T, int NF>
+__device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
+                                         const FaceNbr& fn, double* __restrict__ acc, int h,
+                                         int lane, bool& bad) {
+  const GridArgs& g = s.g;
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const Rsrc Uk = state_rsrc(s.Uk, (uint32_t)(g.nf * fs * sizeof(T)));
+  const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
+  const uint32_t rn_fs = (uint32_t)((size_t)g.n_nodes * CELLS * sizeof(T));
+  const Sources S{Uk, state_rsrc(g.rstate, g.rstate ? (uint32_t)g.nf * rn_fs : 0u), fs_b, rn_fs};
+  const int d = lane >> 5;
+  const int a = lane & 7;
+  const int zz = (lane >> 3) & 3;
+  const Pencil p = make_pencil<T>(g, li, d, a, 4 * h + zz, fn);
+  const int acc_off = d == 0 ? zz * ACC_PLANE + a * ACC_PITCH : zz * ACC_PLANE + a;
+  const int acc_step = d == 0 ? 1 : ACC_PITCH;
+
+  for (int j = lane; j < NF * ACC_HALF / 2; j += 64)
+    reinterpret_cast<double2*>(acc)[j] = make_double2(-0.0, -0.0);
+  wave_lds_sync();
+  Ppm<T> st[NF];
+  double Hprev[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    Hprev[f] = 0.0;
+  }
+  stream_prologue<T, NF>(st, S, p, 0);
+  T qnext[NF];
+  load_position<T, NF>(S, pencil_src(p, 5), qnext);
+#pragma unroll 1
+  for (int k = 5; k < TW; ++k) {
+    T qn[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) qn[f] = qnext[f];
+    if (k + 1 < TW) load_position<T, NF>(S, pencil_src(p, k + 1), qnext);
+    T H[NF];
+    stream_step<T, NF>(ph, d, st, qn, H, bad);
+    if (g.reg && (k == 5 || k == TW - 1)) record_face<T, NF>(g, fn, k - 5, a, 4 * h + zz, H);
+    if (k >= 6) {
+      const int i = k - 6;  // interior cell along d: H now is its high face
+      const int ai = acc_off + i * acc_step;
+      double dH[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) dH[f] = (double)H[f] - Hprev[f];
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        __hip_atomic_fetch_add(&acc[f * ACC_HALF + ai], dH[f], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) Hprev[f] = (double)H[f];
+  }
+}
+
+// Phase Z of half h: lane (x, y) streams its z-pencil over stream positions
+// [4h, 4h+10), which yields the z-faces of cells z in [4h, 4h+4), adds dHz
+// to the accumulator and finishes those cells.
+template <typename T, int NF>
+__device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
+                                        const FaceNbr& fn, const double* __restrict__ acc, int h,
+                                        int lane, double dt, double inv_dx, bool& bad) {
+  const GridArgs& g = s.g;
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const Rsrc Uk = state_rsrc(s.Uk, (uint32_t)(g.nf * fs * sizeof(T)));
+  const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
+  const uint32_t rn_fs = (uint32_t)((size_t)g.n_nodes * CELLS * sizeof(T));
+  const Sources S{Uk, state_rsrc(g.rstate, g.rstate ? (uint32_t)g.nf * rn_fs : 0u), fs_b, rn_fs};
+  const Rsrc U0 = state_rsrc(s.U0 ? s.U0 : s.Uk, (uint32_t)(g.nf * fs * sizeof(T)));
+  const int x = lane & 7, y = lane >> 3;
+  const Pencil p = make_pencil<T>(g, li, 2, x, y, fn);
+  const int k0 = 4 * h;
+  const uint32_t leaf_at = (uint32_t)li.leaf * CELLS + y * 8 + x;
+
+  Ppm<T> st[NF];
+  double Hprev[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    Hprev[f] = 0.0;
+  }
+  stream_prologue<T, NF>(st, S, p, k0);
+  T qnext[NF];
+  load_position<T, NF>(S, pencil_src(p, k0 + 5), qnext);
+#pragma unroll 1
+  for (int kk = 5; kk < 10; ++kk) {
+    const int k = k0 + kk;
+    T qn[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) qn[f] = qnext[f];
+    if (kk + 1 < 10) load_position<T, NF>(S, pencil_src(p, k + 1), qnext);
+    // U0 of the cell this step finishes: issued now, consumed after the
+    // face evaluation, so the load's latency is covered by it
+    T u0v[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) u0v[f] = T(0);
+    if (kk >= 6 && s.U0) {
+      const uint32_t cell_b = (uint32_t)sizeof(T) * (leaf_at + (k - 6) * 64);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) u0v[f] = bload(T(), FieldView{U0, f * fs_b}, cell_b);
+    }
+    T H[NF];
+    stream_step<T, NF>(ph, 2, st, qn, H, bad);
+    if (g.reg && (k == 5 || k == TW - 1)) record_face<T, NF>(g, fn, k - 5, x, y, H);
+    if (kk >= 6) {
+      const int i = k - 6;  // interior cell along z
+      const int ai = (i - k0) * ACC_PLANE + y * ACC_PITCH + x;
+      // rotating-frame sources of s_x, s_y, s_z, E from this cell's Uk
+      double src[4] = {0.0, 0.0, 0.0, 0.0};
+      const bool rot = g.omega != 0.0;
+      if (rot) {
+        const double dx = 1.0 / (double)(SUB * li.blocks);
+        const double rx = ((double)(SUB * li.ix + x) + 0.5) * dx - 0.5;
+        const double ry = ((double)(SUB * li.iy + y) + 0.5) * dx - 0.5;
+        const double rho = (double)st[0].qy, sx = (double)st[1].qy, sy = (double)st[2].qy;
+        const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+        src[0] = tw * sy + rho * om2 * rx;
+        src[1] = rho * om2 * ry - tw * sx;
+        src[3] = om2 * (sx * rx + sy * ry);
+      }
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double sum = acc[f * ACC_HALF + ai] + ((double)H[f] - Hprev[f]);
+        finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, st[f].qy, u0v[f], sum,
+                       rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) Hprev[f] = (double)H[f];
+  }
+}
+
+// W = register budget: W waves per SIMD (1: up to 512 VGPRs, 2: up to 256).
+template <typename T, int NF, int W>
+__global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
+  __shared__ __align__(16) double acc[NF * ACC_HALF];
+  const GridArgs& g = s.g;
+  int bid = blockIdx.x;
+  if (s.remap) {
+    // contiguous (Morton-ordered) leaf ranges per XCD: blocks are dealt to
+    // the 8 XCDs round-robin, so block b runs on XCD b % 8
+    const int n = g.n_leaves, q = n >> 3, r = n & 7;
+    const int xcd = bid & 7, j = bid >> 3;
+    bid = xcd * q + min(xcd, r) + j;
+  }
+  const int leaf = s.leaf_base + bid;
+  if (leaf >= g.n_leaves) return;
+  const int lane = threadIdx.x;
+
+  LeafInfo li;
+  li.leaf = leaf;
+  const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
+  li.ix = c4.y;
+  li.iy = c4.z;
+  li.iz = c4.w;
+  li.blocks = g.base << c4.x;
+  // face-neighbour slots: -x 12, +x 14, -y 10, +y 16, -z 4, +z 22
+  const uint8_t* kd = g.kind + 27 * leaf;
+  const int32_t* nb = g.nbr + 27 * leaf;
+  const bool xlane = lane < 32;  // phase XY: lanes 0-31 x-pencils, 32-63 y-pencils
+  FaceNbr fxy, fz;
+  fxy.klo = xlane ? (int)kd[12] : (int)kd[10];
+  fxy.ilo = xlane ? nb[12] : nb[10];
+  fxy.khi = xlane ? (int)kd[14] : (int)kd[16];
+  fxy.ihi = xlane ? nb[14] : nb[16];
+  fz.klo = kd[4];
+  fz.ilo = nb[4];
+  fz.khi = kd[22];
+  fz.ihi = nb[22];
+  fxy.rlo = fxy.rhi = fxy.flo = fxy.fhi = -1;
+  fz.rlo = fz.rhi = fz.flo = fz.fhi = -1;
+  if (g.reg) {
+    // register slots per face orientation o = 2*axis + side
+    const int32_t* fsl = g.face_slot + 6 * leaf;
+    const int32_t* fin = g.fine_slot + 6 * leaf;
+    fxy.rlo = xlane ? fsl[0] : fsl[2];
+    fxy.rhi = xlane ? fsl[1] : fsl[3];
+    fxy.flo = xlane ? fin[0] : fin[2];
+    fxy.fhi = xlane ? fin[1] : fin[3];
+    fz.rlo = fsl[4];
+    fz.rhi = fsl[5];
+    fz.flo = fin[4];
+    fz.fhi = fin[5];
+  }
+  const double dt = *s.dt;
+  const double inv_dx = (double)(SUB * li.blocks);
+  Phys<T> ph;
+  ph.gamma = (T)g.gamma;
+  ph.gm1 = (T)(g.gamma - 1.0);
+  ph.eta1 = (T)g.eta1;
+
+  bool bad = false;
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    phase_xy<T, NF>(s, ph, li, fxy, acc, h, lane, bad);
+    wave_lds_sync();
+    phase_z<T, NF>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad);
+    wave_lds_sync();
+  }
+  if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
+}
+
+// ---------------------------------------------------------------------------
+// Full three-dimensional reconstruction with face quadrature (Sec. V-B-1: the
+// reconstruct kernel does a full 3D reconstruction, the flux kernel integrates
+// each face's flux by quadrature).
+//
+// Each cell gets values at its 26 face, edge and corner points: the point
+// t + p/2 (p in {-1,0,1}^3, not 0) comes from the PPM of the axis scheme on
+// the 5 cells t + m e, m = -2..2, with e = p or -p (first non-zero component
+// positive): the right end of the cell's parabola when e = p, else the left
+// end.  A face normal to D gets the Kurganov-Tadmor flux at its 9 points
+// (pu, pv) in {-1,0,1}^2 (u < v the other two axes) -- left state from the
+// left cell at (+1, pu, pv)/2, right state from the right cell at
+// (-1, pu, pv)/2 -- combined by the tensor Simpson rule
+//   ((corners + 4 edges) + 16 centre) / 36,
+//   corners = (H(-1,-1) + H(1,1)) + (H(1,-1) + H(-1,1)),
+//   edges   = (H(0,-1) + H(0,1)) + (H(-1,0) + H(1,0)).
+//
+// Ghost cells come from tiles materialised by k_fill (all 26 regions: the
+// diagonal lines reach edge and corner ghosts).
+// ---------------------------------------------------------------------------
+
+// One end of the PPM parabola of the cell at t along a line of tile stride s.
+template <typename T>
+__device__ __forceinline__ T line_end(const T* __restrict__ t, int s, bool right) {
+  const T q0 = t[-2 * s], q1 = t[-s], q2 = t[0], q3 = t[s], q4 = t[2 * s];
+  const T dm1 = limited_slope(q0, q1, q2);
+  const T dm2 = limited_slope(q1, q2, q3);
+  const T dm3 = limited_slope(q2, q3, q4);
+  T l = T(0.5) * (q1 + q2) - (dm2 - dm1) * T(1.0 / 6.0);
+  T r = T(0.5) * (q2 + q3) - (dm3 - dm2) * T(1.0 / 6.0);
+  monotonise(q2, l, r);
+  return right ? r : l;
+}
+
+// Tile stride of the line that gives point p, and whether p is its right end.
+struct PointLine {
+  int s;
+  bool right;
+};
+
+__device__ __forceinline__ constexpr PointLine point_line(int px, int py, int pz) {
+  return PointLine{((px != 0 ? px : (py != 0 ? py : pz)) > 0 ? 1 : -1) *
+                       (px + TW * py + TW * TW * pz),
+                   (px != 0 ? px : (py != 0 ? py : pz)) > 0};
+}
+
+// Point offset components of face point (pu, pv) on side sd (+1 left cell,
+// -1 right cell) of a face normal to D.
+template <int D>
+__device__ __forceinline__ constexpr PointLine face_point(int sd, int pu, int pv) {
+  return D == 0 ? point_line(sd, pu, pv) : (D == 1 ? point_line(pu, sd, pv)
+                                                   : point_line(pu, pv, sd));
+}
+
+// Simpson combination of the 9 point values of one field, points in the
+// order (-1,-1), (1,1), (1,-1), (-1,1), (0,-1), (0,1), (-1,0), (1,0), (0,0).
+template <typename T>
+__device__ __forceinline__ T simpson9(const T (&h)[9]) {
+  const T corners = (h[0] + h[1]) + (h[2] + h[3]);
+  const T edges = (h[4] + h[5]) + (h[6] + h[7]);
+  return ((corners + T(4) * edges) + T(16) * h[8]) / T(36);
+}
+
+// Flux of all fields through the face between tile cells tl and tl + stride
+// of D (Gt: field 0's tile of the leaf, field stride fsG).  The core fields'
+// end values at all 9 points are read first (their loads are independent, so
+// many are in flight at once) and give the points' Kurganov-Tadmor fluxes,
+// velocities and signal speeds; each passive field then uses those speeds.
+template <typename T, int NF, int D>
+__device__ __forceinline__ void face_flux_3d(const Phys<T>& ph, const T* __restrict__ Gt,
+                                             size_t fsG, int tl, T (&H)[NF], bool& bad) {
+  constexpr int SD = D == 0 ? 1 : (D == 1 ? TW : TW * TW);
+  constexpr int PU[9] = {-1, 1, 1, -1, 0, 0, -1, 1, 0};
+  constexpr int PV[9] = {-1, 1, -1, 1, -1, 1, 0, 0, 0};
+  const int tr = tl + SD;
+  T hc[NF_CORE][9], vl[9], vr[9], ha[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const PointLine pl = face_point<D>(1, PU[q], PV[q]);
+    const PointLine pr = face_point<D>(-1, PU[q], PV[q]);
+    T UL[NF_CORE], UR[NF_CORE], Hc[NF_CORE];
+#pragma unroll
+    for (int f = 0; f < NF_CORE; ++f) {
+      UL[f] = line_end(Gt + f * fsG + tl, pl.s, pl.right);
+      UR[f] = line_end(Gt + f * fsG + tr, pr.s, pr.right);
+    }
+    core_flux(ph, D, UL, UR, Hc, vl[q], vr[q], ha[q], bad);
+#pragma unroll
+    for (int f = 0; f < NF_CORE; ++f) hc[f][q] = Hc[f];
+  }
+#pragma unroll
+  for (int f = 0; f < NF_CORE; ++f) H[f] = simpson9(hc[f]);
+#pragma unroll
+  for (int f = NF_CORE; f < NF; ++f) {
+    T h[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const PointLine pl = face_point<D>(1, PU[q], PV[q]);
+      const PointLine pr = face_point<D>(-1, PU[q], PV[q]);
+      const T ul = line_end(Gt + f * fsG + tl, pl.s, pl.right);
+      const T ur = line_end(Gt + f * fsG + tr, pr.s, pr.right);
+      h[q] = T(0.5) * (ul * vl[q] + ur * vr[q]) - ha[q] * (ur - ul);
+    }
+    H[f] = simpson9(h);
+  }
+}
+
+// Face-neighbour register slots of the faces normal to axis D.
+__device__ __forceinline__ FaceNbr face_slots_3d(const GridArgs& g, int leaf, int D) {
+  FaceNbr fn;
+  fn.klo = fn.ilo = fn.khi = fn.ihi = 0;
+  fn.rlo = fn.rhi = fn.flo = fn.fhi = -1;
+  if (g.reg) {
+    fn.rlo = g.face_slot[6 * leaf + 2 * D];
+    fn.rhi = g.face_slot[6 * leaf + 2 * D + 1];
+    fn.flo = g.fine_slot[6 * leaf + 2 * D];
+    fn.fhi = g.fine_slot[6 * leaf + 2 * D + 1];
+  }
+  return fn;
+}
+
+// Tile index of leaf cell (x, y, z); -1 and 8 name the ghost layers.
+__device__ __forceinline__ constexpr int tile_at(int x, int y, int z) {
+  return (x + GH) + (y + GH) * TW + (z + GH) * TW * TW;
+}
+
+// One wave per leaf sweeps the z-planes; lane (x, y) owns cell (x, y, z) of
+// the current plane.  A face's flux depends on no other face, so each plane
+// costs three face evaluations per lane, each of them a wave-wide load of
+// consecutive x-cells: the cell's low x-face, its low y-face and its high
+// z-face.  The high x-face (y-face) of a cell is the low face of lane x+1
+// (y+1), taken by a lane shuffle; for x = 7 (y = 7) it is face 8 of the row
+// (column), which a first pass evaluates for the whole leaf and keeps in LDS.
+// The low z-face is the high z-face of the plane before, kept in registers
+// (z-face 0 comes from the first pass).  The differences are summed
+// ((x + y) + z) in binary64 and the cell is finished as k_step does.
+template <typename T, int NF>
+__global__ void __launch_bounds__(64) k_step3d(StepArgs s, const T* __restrict__ G) {
+  __shared__ double hx8[NF * 64];  // x-face 8 of row (y, z), at z * 8 + y
+  __shared__ double hy8[NF * 64];  // y-face 8 of column (x, z), at z * 8 + x
+  const GridArgs& g = s.g;
+  const int leaf = s.leaf_base + blockIdx.x;
+  if (leaf >= g.n_leaves) return;
+  const int lane = threadIdx.x;
+  LeafInfo li;
+  li.leaf = leaf;
+  const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
+  li.ix = c4.y;
+  li.iy = c4.z;
+  li.iz = c4.w;
+  li.blocks = g.base << c4.x;
+  const double dt = *s.dt;
+  const double inv_dx = (double)(SUB * li.blocks);
+  Phys<T> ph;
+  ph.gamma = (T)g.gamma;
+  ph.gm1 = (T)(g.gamma - 1.0);
+  ph.eta1 = (T)g.eta1;
+  const size_t fsG = (size_t)g.n_leaves * TILE;
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const T* __restrict__ Gt = G + (size_t)leaf * TILE;
+  const FaceNbr fx = face_slots_3d(g, leaf, 0);
+  const FaceNbr fy = face_slots_3d(g, leaf, 1);
+  const FaceNbr fz = face_slots_3d(g, leaf, 2);
+  const int x = lane & 7, y = lane >> 3;
+  bool bad = false;
+  const double dx = 1.0 / (double)(SUB * li.blocks);
+  const double rx = ((double)(SUB * li.ix + x) + 0.5) * dx - 0.5;
+  const double ry = ((double)(SUB * li.iy + y) + 0.5) * dx - 0.5;
+  double Hz[NF];
+  // z = -1 is the first pass: x-face 8 of row (a, b) and y-face 8 of column
+  // (a, b), (a, b) = (lane & 7, lane >> 3), into LDS, and z-face 0 of the
+  // lane's column into Hz.  Each later z evaluates the three faces of the
+  // lane's cell and finishes it.
+#pragma unroll 1
+  for (int z = -1; z < SUB; ++z) {
+    wave_lds_sync();  // the first pass's LDS values are read from z = 0 on
+    const bool first = z < 0;
+    T H[NF];
+    double sxy[NF];
+    face_flux_3d<T, NF, 0>(ph, Gt, fsG, first ? tile_at(SUB - 1, x, y) : tile_at(x - 1, y, z),
+                           H, bad);
+    if (first) {
+      if (g.reg) record_face<T, NF>(g, fx, SUB, x, y, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) hx8[f * 64 + lane] = (double)H[f];
+    } else {
+      if (g.reg && x == 0) record_face<T, NF>(g, fx, 0, y, z, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double lo = (double)H[f];
+        const double up = __shfl_down(lo, 1, 8);  // lane x+1: its low face
+        const double hi = x == SUB - 1 ? hx8[f * 64 + z * 8 + y] : up;
+        sxy[f] = hi - lo;
+      }
+    }
+    face_flux_3d<T, NF, 1>(ph, Gt, fsG, first ? tile_at(x, SUB - 1, y) : tile_at(x, y - 1, z),
+                           H, bad);
+    if (first) {
+      if (g.reg) record_face<T, NF>(g, fy, SUB, x, y, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) hy8[f * 64 + lane] = (double)H[f];
+    } else {
+      if (g.reg && y == 0) record_face<T, NF>(g, fy, 0, x, z, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double lo = (double)H[f];
+        const double up = __shfl_down(lo, 8, 64);  // lane y+1: its low face
+        const double hi = y == SUB - 1 ? hy8[f * 64 + z * 8 + x] : up;
+        sxy[f] = sxy[f] + (hi - lo);
+      }
+    }
+    face_flux_3d<T, NF, 2>(ph, Gt, fsG, tile_at(x, y, z), H, bad);
+    if (first) {
+      if (g.reg) record_face<T, NF>(g, fz, 0, x, y, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) Hz[f] = (double)H[f];
+      continue;
+    }
+    if (g.reg && z == SUB - 1) record_face<T, NF>(g, fz, SUB, x, y, H);
+    const T* __restrict__ ukc = Gt + tile_at(x, y, z);  // the cell's Uk
+    double src[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool rot = g.omega != 0.0;
+    if (rot) {
+      const double rho = (double)ukc[0], sx = (double)ukc[fsG], sy = (double)ukc[2 * fsG];
+      const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+      src[0] = tw * sy + rho * om2 * rx;
+      src[1] = rho * om2 * ry - tw * sx;
+      src[3] = om2 * (sx * rx + sy * ry);
+    }
+    const uint32_t at = (uint32_t)leaf * CELLS + z * 64 + lane;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double sum = sxy[f] + ((double)H[f] - Hz[f]);
+      Hz[f] = (double)H[f];
+      const T u0 = s.U0 ? static_cast<const T*>(s.U0)[(size_t)f * fs + at] : T(0);
+      finish_cell<T>(s, (size_t)f * fs, at, ukc[f * fsG], u0, sum, rot && f >= 1 && f <= 4,
+                     f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+    }
+  }
+  if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
+}
+
+template <typename T, int NF>
+inline hipError_t launch_step_nf(const StepArgs& a, int blocks, int waves, hipStream_t st) {
+  if (waves == 2)
+    hipLaunchKernelGGL((k_step<T, NF, 2>), dim3(blocks), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_step<T, NF, 1>), dim3(blocks), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+inline hipError_t launch_step_t(const StepArgs& a, int blocks, int waves, hipStream_t st) {
+  switch (a.g.nf) {
+    case 6: return launch_step_nf<T, 6>(a, blocks, waves, st);
+    case 7: return launch_step_nf<T, 7>(a, blocks, waves, st);
+    case 8: return launch_step_nf<T, 8>(a, blocks, waves, st);
+    case 9: return launch_step_nf<T, 9>(a, blocks, waves, st);
+    case 10: return launch_step_nf<T, 10>(a, blocks, waves, st);
+    case 11: return launch_step_nf<T, 11>(a, blocks, waves, st);
+    case 12: return launch_step_nf<T, 12>(a, blocks, waves, st);
+    case 13: return launch_step_nf<T, 13>(a, blocks, waves, st);
+    case 14: return launch_step_nf<T, 14>(a, blocks, waves, st);
+    case 15: return launch_step_nf<T, 15>(a, blocks, waves, st);
+    case 16: return launch_step_nf<T, 16>(a, blocks, waves, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Launch of k_step3d<T, NF>.  Its instantiations are explicit, spread over
+// the k_step3d_<precision>_<fields>.hip units, which compile in parallel.
+template <typename T, int NF>
+hipError_t launch_step3d_one(const StepArgs& a, int blocks, const T* G, hipStream_t st) {
+  hipLaunchKernelGGL((k_step3d<T, NF>), dim3(blocks), dim3(64), 0, st, a, G);
+  return hipGetLastError();
+}
+
+#define OCTOHYDRO_3D_EXTERN(T, n) \
+  extern template hipError_t launch_step3d_one<T, n>(const StepArgs&, int, const T*, hipStream_t);
+#define OCTOHYDRO_3D_EXTERN_ALL(T)                                                    \
+  OCTOHYDRO_3D_EXTERN(T, 6) OCTOHYDRO_3D_EXTERN(T, 7) OCTOHYDRO_3D_EXTERN(T, 8)       \
+  OCTOHYDRO_3D_EXTERN(T, 9) OCTOHYDRO_3D_EXTERN(T, 10) OCTOHYDRO_3D_EXTERN(T, 11)     \
+  OCTOHYDRO_3D_EXTERN(T, 12) OCTOHYDRO_3D_EXTERN(T, 13) OCTOHYDRO_3D_EXTERN(T, 14)    \
+  OCTOHYDRO_3D_EXTERN(T, 15) OCTOHYDRO_3D_EXTERN(T, 16)
+OCTOHYDRO_3D_EXTERN_ALL(double)
+OCTOHYDRO_3D_EXTERN_ALL(float)
+#undef OCTOHYDRO_3D_EXTERN_ALL
+#undef OCTOHYDRO_3D_EXTERN
+
+template <typename T>
+inline hipError_t launch_step3d_t(const StepArgs& a, int blocks, const T* G, hipStream_t st) {
+  switch (a.g.nf) {
+#define OCTOHYDRO_CASE3D(n) \
+  case n: return launch_step3d_one<T, n>(a, blocks, G, st);
+    OCTOHYDRO_CASE3D(6) OCTOHYDRO_CASE3D(7) OCTOHYDRO_CASE3D(8) OCTOHYDRO_CASE3D(9)
+    OCTOHYDRO_CASE3D(10) OCTOHYDRO_CASE3D(11) OCTOHYDRO_CASE3D(12) OCTOHYDRO_CASE3D(13)
+    OCTOHYDRO_CASE3D(14) OCTOHYDRO_CASE3D(15) OCTOHYDRO_CASE3D(16)
+#undef OCTOHYDRO_CASE3D
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// One translation unit each.
+hipError_t launch_step_f64(const StepArgs& a, int blocks, int waves, hipStream_t st);
+hipError_t launch_step_f32(const StepArgs& a, int blocks, int waves, hipStream_t st);
+hipError_t launch_step3d(const StepArgs& a, int dtype, int blocks, const void* G, hipStream_t st);
+
+}  // namespace octohydro
