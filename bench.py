@@ -244,23 +244,33 @@ def measured_traffic():
 
 
 def kernel_only(args):
-    """Counter-collection mode: a few later-stage launches of the FP64
-    substep on the 65535-leaf workload, then one device copy of a state
-    array (the copy calibrates the HBM byte counters)."""
+    """Counter-collection mode: a few later-stage launches of the substep on
+    the 65535-leaf workload (FP64; with --recon-3d the 3D step in FP64 and
+    then in FP32, its tiles made once and reused), then one device copy of a
+    state array (the copy calibrates the HBM byte counters)."""
     import torch
 
     from paper_2210_06437_amd import binding as hb
     from paper_2210_06437_amd import inputs
     w = inputs.config5()
-    grid = hb.Grid(w.leaf_coord, w.base, w.nf, hb.HYDRO_F64)
-    U = torch.from_numpy(w.U).to("cuda")
-    A, B = grid.empty_state(), grid.empty_state()
-    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
-    hb.hydro_cfl_dt(grid, U, w.cfl, dt)
-    hb.hydro_step(grid, None, U, A, dt, 1.0)
-    for _ in range(args.steps):
-        hb.hydro_step(grid, U, A, B, dt, 0.25)
-    torch.cuda.synchronize()
+    recon = hb.HYDRO_RECON_3D if args.recon_3d else hb.HYDRO_RECON_AXIS
+    for dtype in ((hb.HYDRO_F64, hb.HYDRO_F32) if args.recon_3d else (hb.HYDRO_F64,)):
+        grid = hb.Grid(w.leaf_coord, w.base, w.nf, dtype, reconstruction=recon)
+        tdt = torch.float64 if dtype == hb.HYDRO_F64 else torch.float32
+        U = torch.from_numpy(w.U).to("cuda").to(tdt)
+        A, B = grid.empty_state(), grid.empty_state()
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        hb.hydro_cfl_dt(grid, U, w.cfl, dt)
+        hb.hydro_step(grid, None, U, A, dt, 1.0)
+        if args.recon_3d:
+            hb.hydro_fill_ghosts(grid, A, grid.ghost_tiles)
+        flags = hb.HYDRO_FLAG_NODES_READY if args.recon_3d else 0
+        for _ in range(args.steps):
+            hb.hydro_step(grid, U, A, B, dt, 0.25, flags=flags)
+        torch.cuda.synchronize()
+        if args.recon_3d and dtype == hb.HYDRO_F64:
+            del grid, U, A, B
+            torch.cuda.empty_cache()
     B.copy_(A)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "kernel-only", "launches": args.steps,
@@ -280,6 +290,8 @@ def main():
                     help="skip the full 3D reconstruction (9-point face quadrature)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="launch only the FP64 substep (for counter collection)")
+    ap.add_argument("--recon-3d", action="store_true",
+                    help="with --kernel-only: launch the 3D step (FP64, then FP32) instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the hydro path here is built and timed on a single "

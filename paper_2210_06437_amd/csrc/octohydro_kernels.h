@@ -934,8 +934,12 @@ __device__ __forceinline__ constexpr int tile_at(int x, int y, int z) {
 // The low z-face is the high z-face of the plane before, kept in registers
 // (z-face 0 comes from the first pass).  The differences are summed
 // ((x + y) + z) in binary64 and the cell is finished as k_step does.
+// Register budget: binary32 tiles at 2 wavefronts per SIMD (256 VGPRs;
+// measured 63 ms vs 89 ms at 1 on the 65535-leaf case), binary64 at 1 (a
+// budget of 2 gains nothing there: 124.5 vs 122.3 ms).
 template <typename T, int NF>
-__global__ void __launch_bounds__(64) k_step3d(StepArgs s, const T* __restrict__ G) {
+__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1)
+    k_step3d(StepArgs s, const T* __restrict__ G) {
   __shared__ double hx8[NF * 64];  // x-face 8 of row (y, z), at z * 8 + y
   __shared__ double hy8[NF * 64];  // y-face 8 of column (x, z), at z * 8 + x
   const GridArgs& g = s.g;
