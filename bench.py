@@ -124,6 +124,35 @@ def time_rk3(torch, hb, w, dtype, steps, warmup):
     return gpu_ms / steps, wall * 1e3 / steps, step_ms
 
 
+def time_rk3_with(torch, hb, w, steps, warmup, **grid_kw):
+    """FP64 RK3 steps (HIP graph) on a grid built with extra options (flux
+    correction, rotating frame): ms per step."""
+    grid = hb.Grid(w.leaf_coord, w.base, w.nf, hb.HYDRO_F64, **grid_kw)
+    A = torch.from_numpy(w.U).to("cuda").contiguous()
+    B, W1, W2 = grid.empty_state(), grid.empty_state(), grid.empty_state()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gAB = hb.Rk3Graph(grid, A, W1, W2, B, w.cfl, dt)
+    gBA = hb.Rk3Graph(grid, B, W1, W2, A, w.cfl, dt)
+    for i in range(warmup):
+        (gAB if i % 2 == 0 else gBA).launch()
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for i in range(steps):
+        (gAB if (warmup + i) % 2 == 0 else gBA).launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    if hb.hydro_check_status(grid) != hb.HYDRO_OK:
+        raise RuntimeError(f"step status: {hb.hydro_last_error()}")
+    slots = int(getattr(grid, "n_slots", 0) or 0)
+    gAB.close()
+    gBA.close()
+    del A, B, W1, W2, grid
+    torch.cuda.empty_cache()
+    return ms, slots
+
+
 def time_rk3_3d(torch, hb, w, steps, warmup):
     """FP64 RK3 steps with the full 3D reconstruction (HIP graph), and the
     3D substep kernel alone in its later-stage form (events; the ghosted
@@ -357,6 +386,23 @@ def main():
                    "alu_frac": ops3 / (kms3 * 1e-3) / ALU_PEAK,
                    "hbm_frac": hbm_bytes_per_leaf_stage(nf, 8, True) * n / (kms3 * 1e-3) / HBM_PEAK}
 
+    # the method's optional terms on the same workload: coarse-fine flux
+    # correction (recorded face fluxes + one k_reflux launch per face
+    # orientation after each substep) and the rotating frame's sources
+    log("FP64 RK3 steps with flux correction, and with the rotating frame")
+    steps_x = max(1, min(args.steps, 5))
+    ms_rf, slots = time_rk3_with(torch, hb, w, steps_x, 1, reflux=True)
+    ms_rot, _ = time_rk3_with(torch, hb, w, steps_x, 1, omega=2.0)
+    extras = {
+        "flux_correction": {"value": cells / (ms_rf * 1e-3), "unit": "cell-updates/s",
+                            "ms_per_step": ms_rf, "steps": steps_x,
+                            "overhead_vs_value": ms_rf / ms64 - 1.0,
+                            "coarse_fine_slots": slots},
+        "rotating_frame": {"value": cells / (ms_rot * 1e-3), "unit": "cell-updates/s",
+                           "ms_per_step": ms_rot, "steps": steps_x, "omega": 2.0,
+                           "overhead_vs_value": ms_rot / ms64 - 1.0},
+    }
+
     per_leaf = None
     if not args.no_per_leaf:
         log("batched vs per-leaf launches on the 21988-leaf octree")
@@ -383,6 +429,7 @@ def main():
         "hbm_frac_rk3_step": 8 * nf * 8 * cells / (ms64 * 1e-3) / HBM_PEAK,
         "fp32_mixed": fp32,
         "recon_3d": recon3d,
+        **extras,
         "per_leaf_vs_batched": per_leaf,
         "cpu_baseline": cpu,
     }
