@@ -924,19 +924,23 @@ __device__ __forceinline__ constexpr int tile_at(int x, int y, int z) {
   return (x + GH) + (y + GH) * TW + (z + GH) * TW * TW;
 }
 
-// One wave per leaf sweeps the z-planes; lane (x, y) owns cell (x, y, z) of
-// the current plane.  A face's flux depends on no other face, so each plane
-// costs three face evaluations per lane, each of them a wave-wide load of
-// consecutive x-cells: the cell's low x-face, its low y-face and its high
-// z-face.  The high x-face (y-face) of a cell is the low face of lane x+1
-// (y+1), taken by a lane shuffle; for x = 7 (y = 7) it is face 8 of the row
-// (column), which a first pass evaluates for the whole leaf and keeps in LDS.
-// The low z-face is the high z-face of the plane before, kept in registers
-// (z-face 0 comes from the first pass).  The differences are summed
-// ((x + y) + z) in binary64 and the cell is finished as k_step does.
-// Register budget: binary32 tiles at 2 wavefronts per SIMD (256 VGPRs;
-// measured 63 ms vs 89 ms at 1 on the 65535-leaf case), binary64 at 1 (a
-// budget of 2 gains nothing there: 124.5 vs 122.3 ms).
+// One wave per leaf; lane (x, y) owns cell (x, y, z) of the current z-plane.
+// A face's flux depends on no other face, so each plane costs three face
+// evaluations per lane, each of them a wave-wide load of consecutive
+// x-cells: the cell's low x-face, its low y-face and its high z-face.  The
+// high x-face (y-face) of a cell is the low face of lane x+1 (y+1), taken by
+// a lane shuffle; for x = 7 (y = 7) it is face 8 of the row (column), which
+// a first pass evaluates for the whole leaf and keeps in LDS.  The low
+// z-face is the high z-face of the plane before (z-face 0 comes from the
+// first pass).  The differences are summed ((x + y) + z) in binary64 and the
+// cell is finished as k_step does.
+// binary64 runs at 1 wavefront per SIMD, two z-halves of three loops (one
+// face orientation per loop): one face evaluation nearly fills the 512
+// registers, and three of them in one loop body spilled 333 VGPRs to memory
+// (80 in this layout; 110.7 vs 122.3 ms on the 65535-leaf case).  binary32
+// runs at 2 wavefronts per SIMD (256 VGPRs; 63 ms vs 89 ms at 1) as one
+// sweep with the three faces in one loop body, whose LDS (11 KB) keeps 8
+// wavefronts per CU where the binary64 layout's 39 KB would allow 4.
 template <typename T, int NF>
 __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1)
     k_step3d(StepArgs s, const T* __restrict__ G) {
@@ -970,6 +974,101 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1)
   const double dx = 1.0 / (double)(SUB * li.blocks);
   const double rx = ((double)(SUB * li.ix + x) + 0.5) * dx - 0.5;
   const double ry = ((double)(SUB * li.iy + y) + 0.5) * dx - 0.5;
+  if constexpr (sizeof(T) == 8) {
+  // binary64: two z-halves, each in three loops over its 4 planes -- x-faces,
+  // y-faces, z-faces -- so that one loop body holds one face evaluation.
+  // Lane (x, y) keeps its cells' dHx + dHy in its own LDS slots (acc3) and
+  // its low z-face flux in hz3.  The first half's loops start with a first
+  // pass (zl = -1): x-face 8 of every row and y-face 8 of every column into
+  // hx8/hy8, z-face 0 of the lane's column into hz3.
+  __shared__ double acc3[NF * 256];  // dHx + dHy of the half's cells, [f][zl * 64 + lane]
+  __shared__ double hz3[NF * 64];    // each lane's low z-face flux, [f][lane]
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    const int z0 = 4 * h, zs = h == 0 ? -1 : 0;
+#pragma unroll 1
+    for (int zl = zs; zl < 4; ++zl) {
+      wave_lds_sync();
+      const bool first = zl < 0;
+      const int z = z0 + zl;
+      T H[NF];
+      face_flux_3d<T, NF, 0>(ph, Gt, fsG, first ? tile_at(SUB - 1, x, y) : tile_at(x - 1, y, z),
+                             H, bad);
+      if (first) {
+        if (g.reg) record_face<T, NF>(g, fx, SUB, x, y, H);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) hx8[f * 64 + lane] = (double)H[f];
+        continue;
+      }
+      if (g.reg && x == 0) record_face<T, NF>(g, fx, 0, y, z, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double lo = (double)H[f];
+        const double up = __shfl_down(lo, 1, 8);  // lane x+1: its low face
+        const double hi = x == SUB - 1 ? hx8[f * 64 + z * 8 + y] : up;
+        acc3[f * 256 + zl * 64 + lane] = hi - lo;
+      }
+    }
+#pragma unroll 1
+    for (int zl = zs; zl < 4; ++zl) {
+      wave_lds_sync();
+      const bool first = zl < 0;
+      const int z = z0 + zl;
+      T H[NF];
+      face_flux_3d<T, NF, 1>(ph, Gt, fsG, first ? tile_at(x, SUB - 1, y) : tile_at(x, y - 1, z),
+                             H, bad);
+      if (first) {
+        if (g.reg) record_face<T, NF>(g, fy, SUB, x, y, H);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) hy8[f * 64 + lane] = (double)H[f];
+        continue;
+      }
+      if (g.reg && y == 0) record_face<T, NF>(g, fy, 0, x, z, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double lo = (double)H[f];
+        const double up = __shfl_down(lo, 8, 64);  // lane y+1: its low face
+        const double hi = y == SUB - 1 ? hy8[f * 64 + z * 8 + x] : up;
+        acc3[f * 256 + zl * 64 + lane] = acc3[f * 256 + zl * 64 + lane] + (hi - lo);
+      }
+    }
+#pragma unroll 1
+    for (int zl = zs; zl < 4; ++zl) {
+      const int z = z0 + zl;
+      T H[NF];
+      face_flux_3d<T, NF, 2>(ph, Gt, fsG, tile_at(x, y, z), H, bad);
+      if (zl < 0) {
+        if (g.reg) record_face<T, NF>(g, fz, 0, x, y, H);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) hz3[f * 64 + lane] = (double)H[f];
+        continue;
+      }
+      if (g.reg && z == SUB - 1) record_face<T, NF>(g, fz, SUB, x, y, H);
+      const T* __restrict__ ukc = Gt + tile_at(x, y, z);  // the cell's Uk
+      double src[4] = {0.0, 0.0, 0.0, 0.0};
+      const bool rot = g.omega != 0.0;
+      if (rot) {
+        const double rho = (double)ukc[0], sx = (double)ukc[fsG], sy = (double)ukc[2 * fsG];
+        const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+        src[0] = tw * sy + rho * om2 * rx;
+        src[1] = rho * om2 * ry - tw * sx;
+        src[3] = om2 * (sx * rx + sy * ry);
+      }
+      const uint32_t at = (uint32_t)leaf * CELLS + z * 64 + lane;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double sum = acc3[f * 256 + zl * 64 + lane] + ((double)H[f] - hz3[f * 64 + lane]);
+        hz3[f * 64 + lane] = (double)H[f];
+        const T u0 = s.U0 ? static_cast<const T*>(s.U0)[(size_t)f * fs + at] : T(0);
+        finish_cell<T>(s, (size_t)f * fs, at, ukc[f * fsG], u0, sum, rot && f >= 1 && f <= 4,
+                       f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+      }
+    }
+  }
+  } else {
+  // binary32: one sweep over the planes, three faces per plane in one loop
+  // body (at 2 wavefronts per SIMD the binary64 layout's 39 KB of LDS would
+  // halve the occupancy)
   double Hz[NF];
   // z = -1 is the first pass: x-face 8 of row (a, b) and y-face 8 of column
   // (a, b), (a, b) = (lane & 7, lane >> 3), into LDS, and z-face 0 of the
@@ -1040,6 +1139,7 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1)
       finish_cell<T>(s, (size_t)f * fs, at, ukc[f * fsG], u0, sum, rot && f >= 1 && f <= 4,
                      f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
     }
+  }
   }
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
 }
