@@ -432,6 +432,19 @@ __device__ __forceinline__ double bload(double, const FieldView& v, uint32_t o) 
 __device__ __forceinline__ float bload(float, const FieldView& v, uint32_t o) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v.r, (int)o, (int)v.fo, 0));
 }
+// A value read once and by no other leaf (U0): loaded with the non-temporal
+// cache policy (bit 1 of the buffer instruction's cache-policy operand on
+// gfx950), so that it does not push halo values out of the L2 (measured
+// about -1 % on the FP64 substep of the 65535-leaf case).
+constexpr int CACHE_NT = 2;
+__device__ __forceinline__ double bload_once(double, const FieldView& v, uint32_t o) {
+  return __builtin_bit_cast(double,
+                            __builtin_amdgcn_raw_buffer_load_b64(v.r, (int)o, (int)v.fo, CACHE_NT));
+}
+__device__ __forceinline__ float bload_once(float, const FieldView& v, uint32_t o) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_raw_buffer_load_b32(v.r, (int)o, (int)v.fo, CACHE_NT));
+}
 
 // The two arrays stream values come from: the stage input (all interior and
 // same-level or coarser ghosts) and the restricted node copies (ghosts on a
@@ -695,7 +708,7 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
     if (kk >= 6 && s.U0) {
       const uint32_t cell_b = (uint32_t)sizeof(T) * (leaf_at + (k - 6) * 64);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) u0v[f] = bload(T(), FieldView{U0, f * fs_b}, cell_b);
+      for (int f = 0; f < NF; ++f) u0v[f] = bload_once(T(), FieldView{U0, f * fs_b}, cell_b);
     }
     T H[NF];
     stream_step<T, NF>(ph, 2, st, qn, H, bad);
