@@ -223,3 +223,115 @@ def test_flux_correction_keeps_uneven_trees_conservative(recon3d):
     assert np.all(np.abs(tot(out) - before) <= 1e-13 * scale)
     out2, _, _ = oracle.rk3_step(T, s.U, 0.4, reflux=False)
     assert np.abs(tot(out2) - before).max() > 1e-9 * scale.max()
+
+
+# -- the face quadrature's weights --------------------------------------------
+#
+# Tensor-product Simpson weights over the 3 x 3 face points, built here from
+# the 1D rule (1, 4, 1)/6 and indexed [pv + 1][pu + 1].
+SIMPSON_1D = np.array([1.0, 4.0, 1.0]) / 6.0
+SIMPSON_2D = np.outer(SIMPSON_1D, SIMPSON_1D)
+# Plausible wrong rules: each is normalised and symmetric in both axes.
+WRONG_RULES = {
+    "1d-simpson-along-u": np.outer([0.0, 1.0, 0.0], SIMPSON_1D),
+    "corners-1-edges-4-centre-4-over-24": np.array([[1, 4, 1], [4, 4, 4], [1, 4, 1]]) / 24.0,
+    "no-corners-edges-1-centre-2-over-6": np.array([[0, 1, 0], [1, 2, 1], [0, 1, 0]]) / 6.0,
+    "midpoint": np.array([[0, 0, 0], [0, 1, 0], [0, 0, 0]], dtype=float),
+    "trapezoid": np.outer([0.25, 0.5, 0.25], [0.25, 0.5, 0.25]),
+}
+
+
+def _face_axes(d):
+    return (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
+
+
+def _point_fluxes(tiles, d, tl):
+    """KT flux at each of the 9 face points [pv + 1][pu + 1][field], from the
+    separately pinned point values (linear exactness, line ends) and the
+    separately pinned point flux."""
+    u, v = _face_axes(d)
+    tr = list(tl)
+    tr[d] += 1
+    H = np.empty((3, 3, tiles.shape[0]))
+    for pv in (-1, 0, 1):
+        for pu in (-1, 0, 1):
+            pl, pr = [0, 0, 0], [0, 0, 0]
+            pl[d], pr[d] = 1, -1
+            pl[u] = pr[u] = pu
+            pl[v] = pr[v] = pv
+            UL = np.array([oracle.point_value(tiles[f], tl, pl) for f in range(tiles.shape[0])])
+            UR = np.array([oracle.point_value(tiles[f], tr, pr) for f in range(tiles.shape[0])])
+            H[pv + 1, pu + 1], bad = oracle.face_flux(d, UL, UR)
+            assert bad == 0
+    return H
+
+
+def _smooth_tiles(seed, nf=8):
+    # a smooth, genuinely 3D state: every face point sees a different state
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(np.arange(TW), np.arange(TW), np.arange(TW), indexing="ij")
+
+    def fld(a0, a):
+        k = rng.uniform(0.2, 0.6, size=3)
+        ph = rng.uniform(0, 2 * np.pi, size=3)
+        return a0 + a * np.sin(k[0] * x + ph[0]) * np.cos(k[1] * y + ph[1]) * np.sin(
+            k[2] * z + ph[2])
+    rho = fld(1.0, 0.3)
+    vx, vy, vz = fld(0.1, 0.4), fld(-0.2, 0.4), fld(0.05, 0.4)
+    p = fld(1.0, 0.2)
+    spec = [rho * fld(0.5, 0.3) for _ in range(nf - 6)]
+    U = inputs.conserved(rho.ravel(), vx.ravel(), vy.ravel(), vz.ravel(), p.ravel(),
+                         species=[s.ravel() for s in spec] if spec else None)
+    return np.ascontiguousarray(U.reshape(nf, TW, TW, TW))
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_face_flux_is_the_tensor_simpson_rule_of_the_point_fluxes(d):
+    tiles = _smooth_tiles(40 + d)
+    tl = [6, 5, 7]
+    Hp = _point_fluxes(tiles, d, tl)
+    H, bad = oracle.face_flux_3d(tiles, d, tl)
+    assert bad == 0
+    want = np.einsum("ab,abf->f", SIMPSON_2D, Hp)
+    scale = np.abs(Hp).max(axis=(0, 1))
+    assert np.all(np.abs(H - want) <= 4e-16 * scale), (H - want) / scale
+    # the data tells the rules apart: every wrong rule misses by far more
+    for name, W in WRONG_RULES.items():
+        miss = np.abs(np.einsum("ab,abf->f", W, Hp) - H) / scale
+        assert miss.max() > 1e-6, name
+
+
+def _species_times_velocity_tiles(d, axis, a, b, s0, s1):
+    # rho = 1 and p = 1 uniform; the normal momentum s_d = s0 + s1 t_axis and
+    # a passive species a + b t_axis, both linear in the tile coordinate of
+    # one transverse axis, so the reconstruction reproduces both exactly at
+    # every face point and the species' point flux is the quadratic
+    # (a + b t)(s0 + s1 t)
+    z, y, x = np.meshgrid(np.arange(TW), np.arange(TW), np.arange(TW), indexing="ij")
+    t = (x, y, z)[axis].astype(float)
+    one = np.ones_like(t)
+    v = [0.0 * one, 0.0 * one, 0.0 * one]
+    v[d] = s0 + s1 * t
+    U = inputs.conserved(one.ravel(), v[0].ravel(), v[1].ravel(), v[2].ravel(), one.ravel(),
+                         species=[(a + b * t).ravel()])
+    return np.ascontiguousarray(U.reshape(7, TW, TW, TW))
+
+
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("which", [0, 1])
+def test_simpson_integrates_a_quadratic_transverse_flux_exactly(d, which):
+    # Simpson's rule is exact for quadratics: the face mean of
+    # (a + b t)(s0 + s1 t) over the cell-wide face [t_c - 1/2, t_c + 1/2] is
+    # (a + b t_c)(s0 + s1 t_c) + b s1 / 12.  The midpoint rule misses the
+    # b s1 / 12 term, a trapezoid rule doubles it.  All inputs are dyadic, so
+    # the nine point fluxes are exact and only the final division rounds.
+    axis = _face_axes(d)[which]
+    a, b, s0, s1 = 4.0, 0.125, 0.5, 0.0625
+    tiles = _species_times_velocity_tiles(d, axis, a, b, s0, s1)
+    tl = [6, 5, 7]
+    H, bad = oracle.face_flux_3d(tiles, d, tl)
+    assert bad == 0
+    tc = float(tl[axis])
+    exact = (a + b * tc) * (s0 + s1 * tc) + b * s1 / 12.0
+    assert abs(H[6] - exact) <= 2e-16 * exact, (H[6], exact)
+    assert abs(b * s1 / 12.0) > 1e4 * 2e-16 * exact  # the quadratic term is resolved
