@@ -219,29 +219,110 @@ def per_leaf_vs_batched(torch, hb, w, reps=2):
     return res
 
 
-def cpu_baseline(w, n_sample_leaves=65535):
-    """The FP64 oracle on the host cores: three substeps over a fixed sample
-    of leaves of the same workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, n_sample_leaves=65535, n_single=2048):
+    """The FP64 oracle on the host cores: three substeps (one RK3 step) over
+    a fixed sample of leaves of the same workload, with all threads, then
+    with one thread on a smaller sample."""
     import numpy as np
 
     import oracle
     T = oracle.Table(w.leaf_coord, w.base)
-    rng = np.random.default_rng(0)
-    n_sample_leaves = min(n_sample_leaves, w.n_leaves)
-    S = np.sort(rng.choice(w.n_leaves, n_sample_leaves, replace=False)).astype(np.int32)
     dt = oracle.cfl_dt(T, w.U, w.cfl)
-    W1 = w.U.copy()
-    W2 = w.U.copy()
-    t0 = time.perf_counter()
-    oracle.step_subset(T, w.U, dt, S, out=W1)
-    oracle.step_subset(T, W1, dt, S, beta=0.25, U0=w.U, out=W2)
-    oracle.step_subset(T, W2, dt, S, beta=2.0 / 3.0, U0=w.U, out=W1)
-    sec = time.perf_counter() - t0
-    cells = n_sample_leaves * 512
-    return {"value": cells / sec, "unit": "cell-updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"3 substeps (one RK3 step) over {n_sample_leaves} of {w.n_leaves} leaves "
-                      f"({cells} cells, 11 fields, FP64), {sec:.1f} s"}
+
+    def run(n_leaves):
+        rng = np.random.default_rng(0)
+        n_leaves = min(n_leaves, w.n_leaves)
+        S = np.sort(rng.choice(w.n_leaves, n_leaves, replace=False)).astype(np.int32)
+        W1 = w.U.copy()
+        W2 = w.U.copy()
+        t0 = time.perf_counter()
+        oracle.step_subset(T, w.U, dt, S, out=W1)
+        oracle.step_subset(T, W1, dt, S, beta=0.25, U0=w.U, out=W2)
+        oracle.step_subset(T, W2, dt, S, beta=2.0 / 3.0, U0=w.U, out=W1)
+        return n_leaves * 512, time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    cells, sec = run(n_sample_leaves)
+    oracle.set_num_threads(1)
+    try:
+        cells1, sec1 = run(n_single)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": cells / sec, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"3 substeps (one RK3 step) over {cells // 512} of {w.n_leaves} leaves "
+                      f"({cells} cells, 11 fields, FP64), {sec:.1f} s on {threads} threads",
+            "single_thread": {"value": cells1 / sec1, "unit": "cell-updates/s", "cores": 1,
+                              "sample": f"one RK3 step over {cells1 // 512} leaves "
+                                        f"({cells1} cells), {sec1:.1f} s"}}
+
+
+def fp32_error(torch, hb, steps=100):
+    """Per-field L1 error of the FP32-mixed path after `steps` RK3 steps of
+    the Sod tube on 16^3 sub-grids (128^3 cells, 6 fields), against the FP64
+    path run beside it with the same time steps (the FP64 path equals the
+    FP64 oracle bit for bit on every parity case), and the drift of the
+    totals of mass and energy."""
+    import numpy as np
+
+    from paper_2210_06437_amd import inputs
+    w = inputs.config4()
+    g64 = hb.Grid(w.leaf_coord, w.base, w.nf, hb.HYDRO_F64)
+    g32 = hb.Grid(w.leaf_coord, w.base, w.nf, hb.HYDRO_F32)
+    A = torch.from_numpy(w.U).to("cuda")
+    a = A.float()
+    S64 = [g64.empty_state() for _ in range(3)]
+    S32 = [g32.empty_state() for _ in range(3)]
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t0 = torch.zeros(w.nf, dtype=torch.float64, device="cuda")
+    t1 = torch.zeros(w.nf, dtype=torch.float64, device="cuda")
+    hb.hydro_totals(g32, a, t0)
+    for _ in range(steps):
+        hb.hydro_rk3_step(g64, A, S64[0], S64[1], S64[2], w.cfl, dt)
+        hb.hydro_rk3_step(g32, a, S32[0], S32[1], S32[2], 0.0, dt)
+        A, S64[2] = S64[2], A
+        a, S32[2] = S32[2], a
+    hb.hydro_totals(g32, a, t1)
+    torch.cuda.synchronize()
+    ref = A.cpu().numpy()
+    got = a.double().cpu().numpy()
+    l1 = np.abs(got - ref).reshape(w.nf, -1).sum(1) / np.abs(ref).reshape(w.nf, -1).sum(1)
+    t0, t1 = t0.cpu().numpy(), t1.cpu().numpy()
+    drift = np.abs(t1 - t0) / np.abs(t0)
+    names = ["rho", "s_x", "s_y", "s_z", "E", "tau"]
+    return {"case": f"Sod tube, 16^3 sub-grids (128^3 cells), 6 fields, {steps} RK3 steps at "
+                    f"CFL 0.4, same time steps on both paths",
+            "l1_per_field": {n: float(x) for n, x in zip(names, l1)},
+            "drift_mass": float(drift[0]), "drift_energy": float(drift[4]),
+            "reference": "FP64 HIP path (bit-identical to the FP64 oracle on every parity case)"}
+
+
+def time_config2(torch, hb, steps, warmup):
+    """FP64 RK3 steps (HIP graph) on the Sod tube with 16^3 sub-grids
+    (128^3 cells, 6 fields): cell-updates/s and the fraction of the HBM peak
+    at 8 nf w algorithmic bytes per cell-update."""
+    from paper_2210_06437_amd import inputs
+    w = inputs.config2()
+    ms, _, kms = time_rk3(torch, hb, w, hb.HYDRO_F64, steps, warmup)
+    cells = w.n_leaves * 512
+    return {"workload": "Sod tube, 16^3 sub-grids = 4096 leaves (128^3 cells), 6 fields, FP64",
+            "value": cells / (ms * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms,
+            "steps": steps, "step_kernel_ms": kms,
+            "hbm_frac_rk3_step": 8 * w.nf * 8 * cells / (ms * 1e-3) / HBM_PEAK,
+            "hbm_frac_step_kernel": hbm_bytes_per_leaf_stage(w.nf, 8, True) * w.n_leaves
+                                    / (kms * 1e-3) / HBM_PEAK}
 
 
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "k_step_turbulence65k_f64_traffic.json")
@@ -274,14 +355,14 @@ def measured_traffic():
 
 def kernel_only(args):
     """Counter-collection mode: a few later-stage launches of the substep on
-    the 65535-leaf workload (FP64; with --recon-3d the 3D step in FP64 and
+    the 65535-leaf workload (or with --sod the 128^3-cell Sod tube) (FP64; with --recon-3d the 3D step in FP64 and
     then in FP32, its tiles made once and reused), then one device copy of a
     state array (the copy calibrates the HBM byte counters)."""
     import torch
 
     from paper_2210_06437_amd import binding as hb
     from paper_2210_06437_amd import inputs
-    w = inputs.config5()
+    w = inputs.config2() if args.sod else inputs.config5()
     recon = hb.HYDRO_RECON_3D if args.recon_3d else hb.HYDRO_RECON_AXIS
     for dtype in ((hb.HYDRO_F64, hb.HYDRO_F32) if args.recon_3d else (hb.HYDRO_F64,)):
         grid = hb.Grid(w.leaf_coord, w.base, w.nf, dtype, reconstruction=recon)
@@ -319,6 +400,8 @@ def main():
                     help="skip the full 3D reconstruction (9-point face quadrature)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="launch only the FP64 substep (for counter collection)")
+    ap.add_argument("--sod", action="store_true",
+                    help="with --kernel-only: the Sod tube on 16^3 sub-grids (6 fields) instead")
     ap.add_argument("--recon-3d", action="store_true",
                     help="with --kernel-only: launch the 3D step (FP64, then FP32) instead")
     args = ap.parse_args()
@@ -362,16 +445,19 @@ def main():
     byts = hbm_bytes_per_leaf_stage(nf, 8, True) * n
     alu_ach = ops / (kms64 * 1e-3)
     hbm_ach = byts / (kms64 * 1e-3)
-    alu = {"bound": "alu", "achieved": alu_ach / 1e12, "peak": ALU_PEAK / 1e12,
-           "unit": "T ops/s (FP64 non-fused)", "frac": alu_ach / ALU_PEAK, "traffic": None,
-           "kernel": "k_step<double,11> (fused substep, later-stage form)",
-           "kernel_ms": kms64, "ops_per_launch": ops}
-    hbm = {"bound": "hbm", "achieved": hbm_ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-           "frac": hbm_ach / HBM_PEAK, "traffic": None, "bytes_per_launch": byts}
     traffic = measured_traffic()
-    alu["traffic"] = hbm["traffic"] = traffic
-    roof = alu if alu["frac"] >= hbm["frac"] else hbm
-    other = hbm if roof is alu else alu
+    # the roofline of the workload's metric: algorithmic HBM bytes of the
+    # dominant kernel per launch over its measured duration
+    roof = {"bound": "hbm", "achieved": hbm_ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": hbm_ach / HBM_PEAK, "traffic": traffic,
+            "kernel": "k_step<double,11> (fused substep, later-stage form)",
+            "kernel_ms": kms64, "bytes_per_launch": byts,
+            "target_frac": 0.6}
+    # the kernel's second ceiling: operations of the method's evaluation
+    # against the non-fused FP64 vector rate
+    alu = {"bound": "alu", "achieved": alu_ach / 1e12, "peak": ALU_PEAK / 1e12,
+           "unit": "T ops/s (FP64 non-fused)", "frac": alu_ach / ALU_PEAK,
+           "ops_per_launch": ops}
 
     recon3d = None
     if not args.no_3d:
@@ -403,6 +489,12 @@ def main():
                            "overhead_vs_value": ms_rot / ms64 - 1.0},
     }
 
+    log("Sod tube, 128^3 cells, FP64")
+    sod = time_config2(torch, hb, args.steps, args.warmup)
+    if fp32 is not None:
+        log("FP32-mixed error after 100 RK3 steps of the Sod tube")
+        fp32["error"] = fp32_error(torch, hb)
+
     per_leaf = None
     if not args.no_per_leaf:
         log("batched vs per-leaf launches on the 21988-leaf octree")
@@ -425,11 +517,12 @@ def main():
                    "leaves": n, "cells": cells, "fields": nf, "rk3_substeps": 3,
                    "hip_graph": True, "host_wall_ms_per_step": wall64},
         "roofline": roof,
-        ("hbm" if roof is alu else "alu"): other,
+        "alu": alu,
         "hbm_frac_rk3_step": 8 * nf * 8 * cells / (ms64 * 1e-3) / HBM_PEAK,
         "fp32_mixed": fp32,
         "recon_3d": recon3d,
         **extras,
+        "sod_128cubed": sod,
         "per_leaf_vs_batched": per_leaf,
         "cpu_baseline": cpu,
     }

@@ -103,6 +103,8 @@ def _load():
     lib.oracle_face_flux_3d.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -110,6 +112,11 @@ def _load():
 def num_threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return _load().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops (for timing it)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def _ptr(a):

@@ -757,3 +757,6 @@ int64_t oracle_step_1d(int32_t n, int nf, const double* U0, const double* Uk, do
 
 /* Threads an OpenMP parallel region of the oracle uses. */
 int oracle_num_threads(void) { return omp_get_max_threads(); }
+
+/* Sets the threads of the oracle's later parallel regions (timing only). */
+void oracle_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

@@ -61,5 +61,6 @@ double oracle_point_value(const double* Tf, const int32_t t[3], const int32_t p[
 int oracle_face_flux_3d(const ogrid* g, const double* T, int d, const int32_t tl[3], double* H);
 
 int oracle_num_threads(void);
+void oracle_set_num_threads(int n);
 
 #endif

@@ -353,6 +353,27 @@ def config5() -> Workload:
     return turbulence(32, 4681, 5)
 
 
+def cold_band(coord: np.ndarray, base: int, nf: int = 6, seed_offset: int = 6,
+              p_cold: float = 1e-6) -> Workload:
+    """Supersonic flow with a cold band: rho = 1 + 0.2 sin(2 pi x) sin(2 pi y)
+    + U(+-1e-3), v = (2 + 0.3 sin(2 pi y), 0.5 sin(2 pi z), 0.1), p = p_cold for
+    0.25 <= z < 0.75 (Mach ~ 1500 there: internal energy ~ 1e-6 of the total)
+    and 0.5 elsewhere; any leaf list.  In the band the internal energy is far
+    below 1e-3 of the total energy, where the dual-energy switch takes the
+    pressure from the entropy tracer."""
+    rng = np.random.default_rng(SEED0 + seed_offset)
+    X, Y, Z = cell_centres(coord, base)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+    rho = rho + rng.uniform(-1e-3, 1e-3, size=rho.shape)
+    vx = 2.0 + 0.3 * np.sin(2 * np.pi * Y)
+    vy = 0.5 * np.sin(2 * np.pi * Z)
+    vz = np.full_like(rho, 0.1)
+    p = np.where((Z >= 0.25) & (Z < 0.75), p_cold, 0.5)
+    species = _dirichlet_species(rng, rho.shape)[: nf - 6] if nf > 6 else None
+    return Workload("supersonic flow with a cold band (dual-energy switch)", base, coord,
+                    conserved(rho, vx, vy, vz, p, species))
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
 
 

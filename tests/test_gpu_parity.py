@@ -214,8 +214,11 @@ def test_fp32_mixed_l1_error_against_fp64_oracle(env):
     got = U.double().cpu().numpy()
     l1 = np.abs(got - Uo).reshape(w.nf, -1).sum(1) / np.abs(Uo).reshape(w.nf, -1).sum(1)
     print("FP32-mixed per-field L1 after 10 RK3 steps:", " ".join(f"{x:.2e}" for x in l1))
-    # rho, E, tau and s_x carry the Sod waves; s_y, s_z are noise of 1e-4
+    # rho, E, tau and s_x carry the Sod waves; s_y, s_z are noise of 1e-4,
+    # whose relative error the binary32 rounding of the O(1) pressure in
+    # their fluxes dominates (2.3e-2 after 100 steps of the 128^3 tube)
     assert np.all(l1[[0, 1, 4, 5]] < 1e-5), l1
+    assert np.all(l1[[2, 3]] < 0.05), l1
     hb.hydro_totals(grid, U, tg)
     drift = np.abs(tg.cpu().numpy() - tot0) / np.maximum(oracle.totals(T, np.abs(w.U)), 1e-300)
     print("FP32-mixed total drift (rho, E):", drift[0], drift[4])
@@ -468,3 +471,63 @@ def test_reused_node_copies_give_the_same_step(env):
     assert torch.equal(a, b)
     ref, _ = oracle.step(T, w.U, dt.item())
     assert np.all(_rel(a.cpu().numpy(), ref) <= TOL64)
+
+
+# -- dual-energy switch --------------------------------------------------------
+
+DUAL_CASES = [("cold-band-base4-nf6", lambda: inputs.cold_band(inputs.uniform_leaves(4), 4)),
+              ("cold-band-amr-base2-nf11",
+               lambda: inputs.cold_band(inputs.blobs(base=2, max_level=2, threshold=0.5).leaf_coord,
+                                        2, nf=11))]
+
+
+@pytest.mark.parametrize("name,make", DUAL_CASES, ids=[c[0] for c in DUAL_CASES])
+def test_dual_energy_branch_matches_oracle(env, name, make):
+    """A supersonic state whose cold band has internal energy ~1e-6 of the
+    total: the EOS takes e = tau^gamma there (pow on the device, libm pow in
+    the oracle).  Binary64 substeps, time step and an RK3 step within 1e-12;
+    the binary32 path's L1 error is printed and bounded."""
+    torch, hb = env
+    w = make()
+    U64 = w.U
+    e = U64[4] - 0.5 * ((U64[1] ** 2 + U64[2] ** 2) + U64[3] ** 2) / U64[0]
+    frac = float((e < 1e-3 * U64[4]).mean())
+    print(f"case {name}: {w.n_leaves} leaves nf={w.nf}, cells in the switch {frac:.2f}",
+          flush=True)
+    assert frac > 0.2
+    grid, T, U = _setup(env, w)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hb.hydro_cfl_dt(grid, U, 0.4, dt)
+    dt_o = oracle.cfl_dt(T, w.U, 0.4)
+    assert abs(dt.item() - dt_o) <= 1e-12 * dt_o, (dt.item(), dt_o)
+    dtd = torch.tensor([dt_o], dtype=torch.float64, device="cuda")
+    out = grid.empty_state()
+    hb.hydro_step(grid, None, U, out, dtd, 1.0)
+    ref, bad = oracle.step(T, w.U, dt_o)
+    assert bad == 0
+    err = _rel(out.cpu().numpy(), ref)
+    print(f"  stage1 rel err {err.max():.3e} bit-exact {np.array_equal(out.cpu().numpy(), ref)}")
+    assert np.all(err <= TOL64), err
+    out2 = grid.empty_state()
+    hb.hydro_step(grid, U, out, out2, dtd, 0.25)
+    ref2, _ = oracle.step(T, ref, dt_o, beta=0.25, U0=w.U)
+    err2 = _rel(out2.cpu().numpy(), ref2)
+    assert np.all(err2 <= TOL64), err2
+    W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
+    hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.4, dt)
+    ref3, dt3, bad = oracle.rk3_step(T, w.U, 0.4)
+    assert bad == 0 and abs(dt.item() - dt3) <= 1e-12 * dt3
+    err3 = _rel(Un.cpu().numpy(), ref3)
+    print(f"  rk3 rel err {err3.max():.3e}")
+    assert np.all(err3 <= TOL64), err3
+    assert hb.hydro_check_status(grid) == hb.HYDRO_OK
+    # binary32 storage: one RK3 step with the oracle's time step
+    grid32, _, U32 = _setup(env, w, dtype=1)
+    W1, W2, Un = grid32.empty_state(), grid32.empty_state(), grid32.empty_state()
+    hb.hydro_rk3_step(grid32, U32, W1, W2, Un, 0.0, torch.tensor([dt3], dtype=torch.float64,
+                                                                  device="cuda"))
+    got = Un.double().cpu().numpy()
+    l1 = np.abs(got - ref3).reshape(w.nf, -1).sum(1) / np.abs(ref3).reshape(w.nf, -1).sum(1)
+    print("  FP32-mixed per-field L1 after one RK3 step:", " ".join(f"{x:.2e}" for x in l1))
+    assert hb.hydro_check_status(grid32) == hb.HYDRO_OK
+    assert np.all(l1 < 1e-5), l1
