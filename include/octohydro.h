@@ -250,9 +250,27 @@ int hydro_cfl_dt(const hydro_grid* grid, const void* U_dev, double cfl, double* 
 /*
  * Conserved totals: totals_dev[f] = sum over cells of U_f * dx_L^3, binary64
  * with double-double (TwoSum) accumulation.  Uses a library-owned scratch
- * buffer (allocated on first use per device).
+ * buffer (allocated on first use per device, grown with hipMalloc when a
+ * larger grid needs more) that every call on that device shares: calls
+ * that overlap in time on one device (two streams, or two host threads)
+ * race on it and must be ordered by the caller.
  */
 int hydro_totals(const hydro_grid* grid, const void* U_dev, double* totals_dev, void* stream);
+
+/*
+ * The same totals for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): same
+ * kernels and summation order, so the same bits as hydro_totals.  Its
+ * partial sums live in a fixed array inside the library (256 KiB per GPU,
+ * room for every grid hydro_totals accepts; a larger request returns
+ * HYDRO_E_ARG), held until the process ends; the call makes no hipMalloc,
+ * hipFree or other allocating call.  The array's device address is looked
+ * up on the first call on each device.  Every call overwrites the partial
+ * sums it reads, so nothing needs clearing between calls, but all calls on
+ * one GPU share the array: calls that overlap in time on one device race.
+ */
+int hydro_totals_noalloc(const hydro_grid* grid, const void* U_dev, double* totals_dev,
+                         void* stream);
 
 /*
  * One SSP-RK3 time step (three substeps, Sec. I):

@@ -5,7 +5,8 @@ library.  PyTorch provides device memory and streams.  If the library has not
 been built, importing this module fails loudly -- there is no fallback.
 
 Entry points keep the C names: hydro_build_table, hydro_fill_ghosts,
-hydro_step, hydro_step_per_leaf, hydro_cfl_dt, hydro_totals, hydro_rk3_step,
+hydro_step, hydro_step_per_leaf, hydro_cfl_dt, hydro_totals, hydro_totals_noalloc,
+hydro_rk3_step,
 hydro_rk3_graph_create / hydro_graph_launch / hydro_graph_destroy,
 hydro_check_status, hydro_last_error, hydro_version.
 """
@@ -37,6 +38,7 @@ EXPORTS = [
     "hydro_cfl_dt", "hydro_totals", "hydro_rk3_step", "hydro_rk3_graph_create",
     "hydro_graph_launch", "hydro_graph_destroy", "hydro_check_status", "hydro_last_error",
     "hydro_version", "hydro_set_option", "hydro_get_option", "hydro_build_reflux",
+    "hydro_totals_noalloc",
 ]
 HYDRO_OPT_WAVES_PER_SIMD, HYDRO_OPT_XCD_REMAP = 1, 2
 
@@ -89,6 +91,7 @@ def _load():
         "hydro_step_per_leaf": ([G, vp, vp, vp, vp, f64, i32, vp], ctypes.c_int),
         "hydro_cfl_dt": ([G, vp, f64, vp, vp], ctypes.c_int),
         "hydro_totals": ([G, vp, vp, vp], ctypes.c_int),
+        "hydro_totals_noalloc": ([G, vp, vp, vp], ctypes.c_int),
         "hydro_rk3_step": ([G, vp, vp, vp, vp, f64, vp, vp], ctypes.c_int),
         "hydro_rk3_graph_create": ([G, vp, vp, vp, vp, f64, vp, ctypes.POINTER(vp)], ctypes.c_int),
         "hydro_graph_launch": ([vp, vp], ctypes.c_int),
@@ -306,6 +309,12 @@ def hydro_cfl_dt(grid: Grid, U, cfl, dt, stream=None):
 def hydro_totals(grid: Grid, U, out, stream=None):
     grid.check_state(U, "U")
     _check(_lib.hydro_totals(ctypes.byref(grid.c), _ptr(U), _ptr(out), _stream(stream)))
+
+
+def hydro_totals_noalloc(grid: Grid, U, out, stream=None):
+    """hydro_totals without any device allocation (fixed library scratch)."""
+    grid.check_state(U, "U")
+    _check(_lib.hydro_totals_noalloc(ctypes.byref(grid.c), _ptr(U), _ptr(out), _stream(stream)))
 
 
 def hydro_rk3_step(grid: Grid, Un, W1, W2, Unext, cfl, dt, stream=None):

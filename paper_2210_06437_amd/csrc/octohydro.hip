@@ -515,6 +515,38 @@ static int scratch_get(size_t bytes, void** out) {
   return HYDRO_OK;
 }
 
+// Partial sums of the allocation-free totals (hydro_totals_noalloc): a fixed
+// device array of the library, one copy per GPU, held until the process
+// ends.  Room for TOT_BLOCKS double-double partials of up to 16 fields
+// (256 KiB).  Host code never passes this name to a kernel: it stands for a
+// host-side shadow, and the device address of each GPU's copy comes from
+// hipGetSymbolAddress (static_scratch below).
+constexpr size_t NOALLOC_DOUBLES = 2 * (size_t)TOT_BLOCKS * 16;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+struct StaticScratch {
+  std::mutex mu;
+  std::vector<double*> ptr;  // device address of `scratch`, per device
+};
+static StaticScratch g_static;
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+static int static_scratch(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_static.mu);
+  if ((int)g_static.ptr.size() <= dev) g_static.ptr.resize(dev + 1, nullptr);
+  if (!g_static.ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(HYDRO_E_HIP, "hipGetSymbolAddress returned no address for the scratch");
+    g_static.ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_static.ptr[dev];
+  return HYDRO_OK;
+}
+
 // stream pool for the per-leaf launch mode (default priority)
 struct StreamPool {
   std::mutex mu;
@@ -653,28 +685,52 @@ int hydro_cfl_dt(const hydro_grid* gr, const void* U, double cfl, double* dt, vo
   return cfl_launch(gr, U, cfl, dt, static_cast<hipStream_t>(stream));
 }
 
-int hydro_totals(const hydro_grid* gr, const void* U, double* totals, void* stream) {
-  clear_error();
-  int rc = check_grid(gr, "hydro_totals");
-  if (rc) return rc;
-  if (!U || !totals) return fail(HYDRO_E_ARG, "hydro_totals: U and totals must be set");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  GridArgs g = grid_args(gr);
-  const int blocks = grid_blocks(g.n_leaves, 1, TOT_BLOCKS);
-  void* part = nullptr;
-  rc = scratch_get(sizeof(double) * 2 * (size_t)blocks * g.nf, &part);
-  if (rc) return rc;
-  if (gr->dtype == HYDRO_F64)
+// The two passes of the totals over partial sums at `part` (2 * blocks * nf
+// doubles, every one of them written by the first pass before the second
+// reads it: nothing needs clearing).
+static int totals_launch(const GridArgs& g, int dtype, const void* U, double* part, int blocks,
+                         double* totals, hipStream_t st) {
+  if (dtype == HYDRO_F64)
     hipLaunchKernelGGL(k_totals<double>, dim3(blocks), dim3(TOT_THREADS), 0, st, g,
-                       static_cast<const double*>(U), static_cast<double*>(part));
+                       static_cast<const double*>(U), part);
   else
     hipLaunchKernelGGL(k_totals<float>, dim3(blocks), dim3(TOT_THREADS), 0, st, g,
-                       static_cast<const float*>(U), static_cast<double*>(part));
+                       static_cast<const float*>(U), part);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(TOT_THREADS), 0, st,
                      static_cast<const double*>(part), blocks, g.nf, totals);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
+}
+
+int hydro_totals(const hydro_grid* gr, const void* U, double* totals, void* stream) {
+  clear_error();
+  int rc = check_grid(gr, "hydro_totals");
+  if (rc) return rc;
+  if (!U || !totals) return fail(HYDRO_E_ARG, "hydro_totals: U and totals must be set");
+  GridArgs g = grid_args(gr);
+  const int blocks = grid_blocks(g.n_leaves, 1, TOT_BLOCKS);
+  void* part = nullptr;
+  rc = scratch_get(sizeof(double) * 2 * (size_t)blocks * g.nf, &part);
+  if (rc) return rc;
+  return totals_launch(g, gr->dtype, U, static_cast<double*>(part), blocks, totals,
+                       static_cast<hipStream_t>(stream));
+}
+
+int hydro_totals_noalloc(const hydro_grid* gr, const void* U, double* totals, void* stream) {
+  clear_error();
+  int rc = check_grid(gr, "hydro_totals_noalloc");
+  if (rc) return rc;
+  if (!U || !totals) return fail(HYDRO_E_ARG, "hydro_totals_noalloc: U and totals must be set");
+  GridArgs g = grid_args(gr);
+  const int blocks = grid_blocks(g.n_leaves, 1, TOT_BLOCKS);
+  const size_t need = 2 * (size_t)blocks * g.nf;
+  if (need > NOALLOC_DOUBLES)
+    return fail(HYDRO_E_ARG, "hydro_totals_noalloc: %zu partial sums exceed the fixed %zu", need,
+                NOALLOC_DOUBLES);
+  double* part = nullptr;
+  if ((rc = static_scratch(&part))) return rc;
+  return totals_launch(g, gr->dtype, U, part, blocks, totals, static_cast<hipStream_t>(stream));
 }
 
 int hydro_rk3_step(const hydro_grid* gr, const void* Un, void* W1, void* W2, void* Unext,

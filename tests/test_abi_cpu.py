@@ -115,6 +115,8 @@ def test_entry_points_reject_bad_grids_on_the_host(hb, field, value):
     assert lib.hydro_fill_ghosts(ctypes.byref(g), p, ctypes.c_void_p(128), None) == hb.HYDRO_E_ARG
     assert lib.hydro_cfl_dt(ctypes.byref(g), p, 0.4, p, None) == hb.HYDRO_E_ARG
     assert hb.hydro_last_error()
+    assert lib.hydro_totals_noalloc(ctypes.byref(g), p, p, None) == hb.HYDRO_E_ARG
+    assert "hydro_totals_noalloc" in hb.hydro_last_error()
 
 
 def test_step_rejects_aliasing_and_flags_on_the_host(hb):
