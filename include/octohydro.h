@@ -311,11 +311,17 @@ const char* hydro_last_error(void);
  *   HYDRO_OPT_WAVES_PER_SIMD  1 or 2: register budget of the kernel (2 waves
  *                             per SIMD caps it at 256 VGPRs, which may spill)
  *   HYDRO_OPT_XCD_REMAP       0 or 1: give each XCD a contiguous leaf range
- * Options are process-wide and take effect at the next launch (a captured
+ *   HYDRO_OPT_WAVES_PER_LEAF  1 or 2: wavefronts per leaf; with 2 (n_fields
+ *                             > 6 only) the second wavefront of each leaf
+ *                             evolves the passive species, taking each face's
+ *                             velocities and signal speed from the first
+ *                             through LDS (same bits, half the registers)
+ * Every choice computes the same bits.  Options are process-wide and take effect at the next launch (a captured
  * graph keeps the kernel it was captured with).  Host only, thread-safe.
  */
 #define HYDRO_OPT_WAVES_PER_SIMD 1
 #define HYDRO_OPT_XCD_REMAP 2
+#define HYDRO_OPT_WAVES_PER_LEAF 3
 int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t value);
 int hydro_get_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t* value);
 

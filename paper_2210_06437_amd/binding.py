@@ -40,7 +40,7 @@ EXPORTS = [
     "hydro_version", "hydro_set_option", "hydro_get_option", "hydro_build_reflux",
     "hydro_totals_noalloc",
 ]
-HYDRO_OPT_WAVES_PER_SIMD, HYDRO_OPT_XCD_REMAP = 1, 2
+HYDRO_OPT_WAVES_PER_SIMD, HYDRO_OPT_XCD_REMAP, HYDRO_OPT_WAVES_PER_LEAF = 1, 2, 3
 
 
 class HydroError(RuntimeError):
@@ -128,6 +128,8 @@ def apply_tuning(path: str = TUNING_PATH) -> int:
     for e in data.get("entries", []):
         _lib.hydro_set_option(int(e["dtype"]), int(e["n_fields"]), 1, int(e["waves_per_simd"]))
         _lib.hydro_set_option(int(e["dtype"]), int(e["n_fields"]), 2, int(e["xcd_remap"]))
+        _lib.hydro_set_option(int(e["dtype"]), int(e["n_fields"]), 3,
+                              int(e.get("waves_per_leaf", 1)))
         n += 1
     return n
 

@@ -4,8 +4,8 @@
 
 namespace octohydro {
 
-hipError_t launch_step_f32(const StepArgs& a, int blocks, int waves, hipStream_t st) {
-  return launch_step_t<float>(a, blocks, waves, st);
+hipError_t launch_step_f32(const StepArgs& a, int blocks, StepShape sh, hipStream_t st) {
+  return launch_step_t<float>(a, blocks, sh, st);
 }
 
 }  // namespace octohydro

@@ -358,6 +358,7 @@ static int restrict_launch(const hydro_grid* gr, const void* Uk, hipStream_t st)
 struct Options {
   int waves_per_simd = 1;
   int xcd_remap = 1;
+  int waves_per_leaf = 1;
 };
 static Options g_opts[2][17];
 static std::mutex g_opts_mu;
@@ -370,8 +371,9 @@ static Options get_options(int dtype, int nf) {
 static hipError_t launch_step(StepArgs a, int dtype, int blocks, hipStream_t st) {
   const Options o = get_options(dtype, a.g.nf);
   if (a.remap) a.remap = o.xcd_remap;
-  return dtype == HYDRO_F64 ? launch_step_f64(a, blocks, o.waves_per_simd, st)
-                            : launch_step_f32(a, blocks, o.waves_per_simd, st);
+  const StepShape sh{o.waves_per_simd, o.waves_per_leaf};
+  return dtype == HYDRO_F64 ? launch_step_f64(a, blocks, sh, st)
+                            : launch_step_f32(a, blocks, sh, st);
 }
 
 static int validate_table(const hydro_grid* gr, hipStream_t st) {
@@ -585,6 +587,13 @@ int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t va
       if (value != 0 && value != 1) return fail(HYDRO_E_ARG, "hydro_set_option: remap is 0 or 1");
       o.xcd_remap = value;
       return HYDRO_OK;
+    case HYDRO_OPT_WAVES_PER_LEAF:
+      if (value != 1 && value != 2)
+        return fail(HYDRO_E_ARG, "hydro_set_option: wavefronts per leaf must be 1 or 2");
+      if (value == 2 && n_fields == NF_CORE)
+        return fail(HYDRO_E_ARG, "hydro_set_option: 2 wavefronts per leaf need passive species");
+      o.waves_per_leaf = value;
+      return HYDRO_OK;
     default:
       return fail(HYDRO_E_ARG, "hydro_set_option: unknown option %d", option);
   }
@@ -597,6 +606,7 @@ int hydro_get_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t* v
   const Options o = get_options(dtype, n_fields);
   if (option == HYDRO_OPT_WAVES_PER_SIMD) *value = o.waves_per_simd;
   else if (option == HYDRO_OPT_XCD_REMAP) *value = o.xcd_remap;
+  else if (option == HYDRO_OPT_WAVES_PER_LEAF) *value = o.waves_per_leaf;
   else return fail(HYDRO_E_ARG, "hydro_get_option: unknown option %d", option);
   return HYDRO_OK;
 }

@@ -24,9 +24,8 @@ constexpr int NF_CORE = 6;  // rho, sx, sy, sz, E, tau
 constexpr int ACC_PITCH = 9;  // LDS row pitch (doubles) of the accumulator
 constexpr int ACC_PLANE = SUB * ACC_PITCH;
 constexpr int ACC_FIELD = SUB * ACC_PLANE;
-// A buffer offset past the end of every array the kernels address (array
-// sizes are bounded below it on the host): a buffer load there returns 0
-// without touching memory.
+// Bound on the byte size of every array the kernels address with 32-bit
+// offsets (buffer resources and 32-bit lane offsets); checked on the host.
 constexpr uint32_t OFF_NONE = 0xFFFFF000u;
 
 struct GridArgs {
@@ -385,8 +384,6 @@ __device__ __forceinline__ Pencil make_pencil(const GridArgs& g, const LeafInfo&
 // over the six values.
 struct Src {
   uint32_t o;    // offset of the value in its array
-  uint32_t ouk;  // offset into the stage input, OFF_NONE on a refined side
-  uint32_t orn;  // offset into the node copies, OFF_NONE elsewhere
   bool ref;      // this lane's value comes from a node copy
   bool any_ref;  // some lane of the wave reads a node copy (wave-uniform)
 };
@@ -394,8 +391,7 @@ struct Src {
 __device__ __forceinline__ Src pencil_src(const Pencil& p, int k) {
   Src s;
   if (k >= GH && k < GH + SUB) {
-    s.o = s.ouk = p.off + (uint32_t)(k - GH) * p.sd;
-    s.orn = OFF_NONE;
+    s.o = p.off + (uint32_t)(k - GH) * p.sd;
     s.ref = s.any_ref = false;
     return s;
   }
@@ -403,8 +399,6 @@ __device__ __forceinline__ Src pencil_src(const Pencil& p, int k) {
       : k == 11 ? p.gofs[3] : k == 12 ? p.gofs[4] : p.gofs[5];
   s.ref = k < GH ? p.ref_lo : p.ref_hi;
   s.any_ref = k < GH ? p.any_lo : p.any_hi;
-  s.ouk = s.ref ? OFF_NONE : s.o;
-  s.orn = s.ref ? s.o : OFF_NONE;
   return s;
 }
 
@@ -452,22 +446,39 @@ __device__ __forceinline__ float bload_once(float, const FieldView& v, uint32_t 
 struct Sources {
   Rsrc uk, rn;
   uint32_t uk_fs, rn_fs;
+  const char* uk_ptr;  // the same two arrays as plain addresses
+  const char* rn_ptr;
 };
 
+__device__ __forceinline__ Sources make_sources(const void* Uk, const void* rstate, int nf,
+                                                uint32_t uk_fs, uint32_t rn_fs) {
+  return Sources{state_rsrc(Uk, (uint32_t)nf * uk_fs),
+                 state_rsrc(rstate, rstate ? (uint32_t)nf * rn_fs : 0u), uk_fs, rn_fs,
+                 static_cast<const char*>(Uk), static_cast<const char*>(rstate)};
+}
+
+// One field value at byte offset o of a field array starting at p.
+template <typename T>
+__device__ __forceinline__ T gload(const char* p, uint32_t o) {
+  return *reinterpret_cast<const T*>(p + o);
+}
+
 // The values of a stream position in all NF fields.  Where some lane of the
-// wave reads a node copy, every lane loads from both arrays, one load with
-// an offset past the end (which reads 0 without a memory access), and keeps
-// its own: no divergent branch.  The test is made once per position, not
-// once per field.
+// wave reads a node copy, the lanes read from two arrays: each lane forms
+// the address of its own value in its own array (a 64-bit base and field
+// stride picked once per position) and every field is one plain load, all
+// issued before any is used.  (A buffer load takes its array from scalar
+// registers, so reading both arrays with buffer loads takes two loads and a
+// select per field, which the compiler serialised with a full memory wait
+// per field: 11 memory latencies per such position.)  The test is made
+// once per position, not once per field.
 template <typename T, int NF>
 __device__ __forceinline__ void load_position(const Sources& S, const Src& s, T (&q)[NF]) {
   if (s.any_ref) {
+    const char* base = (s.ref ? S.rn_ptr : S.uk_ptr) + s.o;
+    const uint32_t fsb = s.ref ? S.rn_fs : S.uk_fs;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const T a = bload(T(), FieldView{S.uk, f * S.uk_fs}, s.ouk);
-      const T b = bload(T(), FieldView{S.rn, f * S.rn_fs}, s.orn);
-      q[f] = s.ref ? b : a;
-    }
+    for (int f = 0; f < NF; ++f) q[f] = gload<T>(base, f * fsb);
   } else {
 #pragma unroll
     for (int f = 0; f < NF; ++f) q[f] = bload(T(), FieldView{S.uk, f * S.uk_fs}, s.o);
@@ -615,10 +626,9 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
                                          int lane, bool& bad) {
   const GridArgs& g = s.g;
   const size_t fs = (size_t)g.n_leaves * CELLS;
-  const Rsrc Uk = state_rsrc(s.Uk, (uint32_t)(g.nf * fs * sizeof(T)));
   const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
   const uint32_t rn_fs = (uint32_t)((size_t)g.n_nodes * CELLS * sizeof(T));
-  const Sources S{Uk, state_rsrc(g.rstate, g.rstate ? (uint32_t)g.nf * rn_fs : 0u), fs_b, rn_fs};
+  const Sources S = make_sources(s.Uk, g.rstate, g.nf, fs_b, rn_fs);
   const int d = lane >> 5;
   const int a = lane & 7;
   const int zz = (lane >> 3) & 3;
@@ -673,10 +683,9 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
                                         int lane, double dt, double inv_dx, bool& bad) {
   const GridArgs& g = s.g;
   const size_t fs = (size_t)g.n_leaves * CELLS;
-  const Rsrc Uk = state_rsrc(s.Uk, (uint32_t)(g.nf * fs * sizeof(T)));
   const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
   const uint32_t rn_fs = (uint32_t)((size_t)g.n_nodes * CELLS * sizeof(T));
-  const Sources S{Uk, state_rsrc(g.rstate, g.rstate ? (uint32_t)g.nf * rn_fs : 0u), fs_b, rn_fs};
+  const Sources S = make_sources(s.Uk, g.rstate, g.nf, fs_b, rn_fs);
   const Rsrc U0 = state_rsrc(s.U0 ? s.U0 : s.Uk, (uint32_t)(g.nf * fs * sizeof(T)));
   const int x = lane & 7, y = lane >> 3;
   const Pencil p = make_pencil<T>(g, li, 2, x, y, fn);
@@ -806,6 +815,332 @@ __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
     phase_xy<T, NF>(s, ph, li, fxy, acc, h, lane, bad);
     wave_lds_sync();
     phase_z<T, NF>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad);
+    wave_lds_sync();
+  }
+  if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
+}
+
+// ---------------------------------------------------------------------------
+// Two wavefronts per leaf.  The fields of a leaf are split between the two
+// wavefronts of a 128-thread workgroup: wavefront 0 streams the six core
+// fields (rho, s, E, tau) and evaluates the EOS and the Kurganov-Tadmor core
+// flux at every face, wavefront 1 streams the passive species.  A species
+// flux needs the face's normal velocities and half its signal speed, which
+// wavefront 0 hands over through LDS: a double buffer whose slot alternates
+// with every stream step of the leaf, one workgroup barrier per step (the
+// slot wavefront 0 fills next was read by wavefront 1 before it reached the
+// barrier that wavefront 0 has just passed).  Each wavefront accumulates and
+// finishes its own fields (disjoint LDS accumulator ranges, wave-local
+// hand-offs), so a field's arithmetic is exactly that of k_step.  Half the
+// fields per wavefront halves the register set, which lets two wavefronts
+// share a SIMD and hide each other's memory and dependency latency.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct SpeedSlot {
+  T v[3][64];  // normal velocity left, right, half the signal speed; per lane
+};
+
+// Stream values of fields [F0, F0 + NG) at one position (see load_position).
+template <typename T, int F0, int NG>
+__device__ __forceinline__ void load_group(const Sources& S, const Src& s, T (&q)[NG]) {
+  if (s.any_ref) {
+    const char* base = (s.ref ? S.rn_ptr : S.uk_ptr) + s.o;
+    const uint32_t fsb = s.ref ? S.rn_fs : S.uk_fs;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) q[i] = gload<T>(base, (F0 + i) * fsb);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) q[i] = bload(T(), FieldView{S.uk, (F0 + i) * S.uk_fs}, s.o);
+  }
+}
+
+template <typename T, int F0, int NG>
+__device__ __forceinline__ void prologue_group(Ppm<T> (&st)[NG], const Sources& S,
+                                               const Pencil& p, int k0) {
+  T cur[NG], nxt[NG];
+  load_group<T, F0, NG>(S, pencil_src(p, k0), cur);
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    if (j + 1 < 5) load_group<T, F0, NG>(S, pencil_src(p, k0 + j + 1), nxt);
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      T ul, ur;
+      ppm_push(st[f], cur[f], j, ul, ur);
+      cur[f] = nxt[f];
+    }
+  }
+}
+
+// Fluxes of fields [F0, F0 + NG) through face `face` of a pencil, recorded
+// for the coarse-fine correction (see record_face).
+template <typename T, int NF, int F0, int NG>
+__device__ __forceinline__ void record_group(const GridArgs& g, const FaceNbr& fn, int face,
+                                             int u, int v, const T (&H)[NG]) {
+  const int cs = face == 0 ? fn.rlo : fn.rhi;
+  const int fe = face == 0 ? fn.flo : fn.fhi;
+  if (cs >= 0) {
+    double* r = g.reg + (size_t)cs * NF * REG_STRIDE + u + 8 * v;
+#pragma unroll
+    for (int f = 0; f < NG; ++f) r[(F0 + f) * REG_STRIDE] = (double)H[f];
+  }
+  if (fe >= 0) {
+    const int q = fe & 3;
+    double* r = g.reg + (size_t)(fe >> 2) * NF * REG_STRIDE + REG_COARSE +
+                (8 * (q & 1) + u) + 16 * (8 * (q >> 1) + v);
+#pragma unroll
+    for (int f = 0; f < NG; ++f) r[(F0 + f) * REG_STRIDE] = (double)H[f];
+  }
+}
+
+// One steady stream step of a wavefront's field group: feed qn, evaluate the
+// face (core group: EOS + core flux, speeds handed over; species group:
+// speeds taken over) and return the group's fluxes in H.  Exactly one
+// workgroup barrier per call in either group.
+template <typename T, int F0, int NG>
+__device__ __forceinline__ void group_step(const Phys<T>& ph, int d, Ppm<T> (&st)[NG],
+                                           const T (&qn)[NG], T (&H)[NG],
+                                           SpeedSlot<T>* __restrict__ spd, int slot, int lane,
+                                           bool& bad) {
+  if constexpr (F0 == 0) {
+    static_assert(NG == NF_CORE, "the core group is the six core fields");
+    T core_L[NF_CORE], core_R[NF_CORE], vL, vR, ha;
+#pragma unroll
+    for (int f = 0; f < NF_CORE; ++f) {
+      ppm_push(st[f], qn[f], 5, core_L[f], core_R[f]);
+      OCTOHYDRO_FENCE();
+    }
+    core_flux(ph, d, core_L, core_R, H, vL, vR, ha, bad);
+    spd[slot].v[0][lane] = vL;
+    spd[slot].v[1][lane] = vR;
+    spd[slot].v[2][lane] = ha;
+    __syncthreads();
+  } else {
+    T ul[NG], ur[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) {
+      ppm_push(st[f], qn[f], 5, ul[f], ur[f]);
+      OCTOHYDRO_FENCE();
+    }
+    __syncthreads();
+    const T vL = spd[slot].v[0][lane], vR = spd[slot].v[1][lane], ha = spd[slot].v[2][lane];
+#pragma unroll
+    for (int f = 0; f < NG; ++f)
+      H[f] = T(0.5) * (ul[f] * vL + ur[f] * vR) - ha * (ur[f] - ul[f]);
+  }
+}
+
+// Phase XY of half h for one field group (see phase_xy).
+template <typename T, int NF, int F0, int NG>
+__device__ __forceinline__ void phase_xy_group(const StepArgs& s, const Phys<T>& ph,
+                                               const LeafInfo& li, const FaceNbr& fn,
+                                               double* __restrict__ acc,
+                                               SpeedSlot<T>* __restrict__ spd, int& sn, int h,
+                                               int lane, bool& bad) {
+  const GridArgs& g = s.g;
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
+  const uint32_t rn_fs = (uint32_t)((size_t)g.n_nodes * CELLS * sizeof(T));
+  const Sources S = make_sources(s.Uk, g.rstate, g.nf, fs_b, rn_fs);
+  const int d = lane >> 5;
+  const int a = lane & 7;
+  const int zz = (lane >> 3) & 3;
+  const Pencil p = make_pencil<T>(g, li, d, a, 4 * h + zz, fn);
+  const int acc_off = d == 0 ? zz * ACC_PLANE + a * ACC_PITCH : zz * ACC_PLANE + a;
+  const int acc_step = d == 0 ? 1 : ACC_PITCH;
+
+  double2* mine = reinterpret_cast<double2*>(acc + F0 * ACC_HALF);
+  for (int j = lane; j < NG * ACC_HALF / 2; j += 64) mine[j] = make_double2(-0.0, -0.0);
+  wave_lds_sync();
+  Ppm<T> st[NG];
+  double Hprev[NG];
+#pragma unroll
+  for (int f = 0; f < NG; ++f) {
+    st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    Hprev[f] = 0.0;
+  }
+  prologue_group<T, F0, NG>(st, S, p, 0);
+  T qnext[NG];
+  load_group<T, F0, NG>(S, pencil_src(p, 5), qnext);
+#pragma unroll 1
+  for (int k = 5; k < TW; ++k) {
+    T qn[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) qn[f] = qnext[f];
+    if (k + 1 < TW) load_group<T, F0, NG>(S, pencil_src(p, k + 1), qnext);
+    T H[NG];
+    group_step<T, F0, NG>(ph, d, st, qn, H, spd, sn & 1, lane, bad);
+    ++sn;
+    if (g.reg && (k == 5 || k == TW - 1))
+      record_group<T, NF, F0, NG>(g, fn, k - 5, a, 4 * h + zz, H);
+    if (k >= 6) {
+      const int ai = acc_off + (k - 6) * acc_step;
+      double dH[NG];
+#pragma unroll
+      for (int f = 0; f < NG; ++f) dH[f] = (double)H[f] - Hprev[f];
+#pragma unroll
+      for (int f = 0; f < NG; ++f)
+        __hip_atomic_fetch_add(&acc[(F0 + f) * ACC_HALF + ai], dH[f], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+#pragma unroll
+    for (int f = 0; f < NG; ++f) Hprev[f] = (double)H[f];
+  }
+}
+
+// Phase Z of half h for one field group (see phase_z); the core group adds
+// the rotating-frame sources.
+template <typename T, int NF, int F0, int NG>
+__device__ __forceinline__ void phase_z_group(const StepArgs& s, const Phys<T>& ph,
+                                              const LeafInfo& li, const FaceNbr& fn,
+                                              const double* __restrict__ acc,
+                                              SpeedSlot<T>* __restrict__ spd, int& sn, int h,
+                                              int lane, double dt, double inv_dx, bool& bad) {
+  const GridArgs& g = s.g;
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
+  const uint32_t rn_fs = (uint32_t)((size_t)g.n_nodes * CELLS * sizeof(T));
+  const Sources S = make_sources(s.Uk, g.rstate, g.nf, fs_b, rn_fs);
+  const Rsrc U0 = state_rsrc(s.U0 ? s.U0 : s.Uk, (uint32_t)(g.nf * fs * sizeof(T)));
+  const int x = lane & 7, y = lane >> 3;
+  const Pencil p = make_pencil<T>(g, li, 2, x, y, fn);
+  const int k0 = 4 * h;
+  const uint32_t leaf_at = (uint32_t)li.leaf * CELLS + y * 8 + x;
+
+  Ppm<T> st[NG];
+  double Hprev[NG];
+#pragma unroll
+  for (int f = 0; f < NG; ++f) {
+    st[f] = Ppm<T>{T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    Hprev[f] = 0.0;
+  }
+  prologue_group<T, F0, NG>(st, S, p, k0);
+  T qnext[NG];
+  load_group<T, F0, NG>(S, pencil_src(p, k0 + 5), qnext);
+#pragma unroll 1
+  for (int kk = 5; kk < 10; ++kk) {
+    const int k = k0 + kk;
+    T qn[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) qn[f] = qnext[f];
+    if (kk + 1 < 10) load_group<T, F0, NG>(S, pencil_src(p, k + 1), qnext);
+    T u0v[NG];
+#pragma unroll
+    for (int f = 0; f < NG; ++f) u0v[f] = T(0);
+    if (kk >= 6 && s.U0) {
+      const uint32_t cell_b = (uint32_t)sizeof(T) * (leaf_at + (k - 6) * 64);
+#pragma unroll
+      for (int f = 0; f < NG; ++f)
+        u0v[f] = bload_once(T(), FieldView{U0, (F0 + f) * fs_b}, cell_b);
+    }
+    T H[NG];
+    group_step<T, F0, NG>(ph, 2, st, qn, H, spd, sn & 1, lane, bad);
+    ++sn;
+    if (g.reg && (k == 5 || k == TW - 1)) record_group<T, NF, F0, NG>(g, fn, k - 5, x, y, H);
+    if (kk >= 6) {
+      const int i = k - 6;  // interior cell along z
+      const int ai = (i - k0) * ACC_PLANE + y * ACC_PITCH + x;
+      double src[4] = {0.0, 0.0, 0.0, 0.0};
+      const bool rot = F0 == 0 && g.omega != 0.0;
+      if (rot) {
+        const double dx = 1.0 / (double)(SUB * li.blocks);
+        const double rx = ((double)(SUB * li.ix + x) + 0.5) * dx - 0.5;
+        const double ry = ((double)(SUB * li.iy + y) + 0.5) * dx - 0.5;
+        const double rho = (double)st[0].qy, sx = (double)st[1].qy, sy = (double)st[2].qy;
+        const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+        src[0] = tw * sy + rho * om2 * rx;
+        src[1] = rho * om2 * ry - tw * sx;
+        src[3] = om2 * (sx * rx + sy * ry);
+      }
+#pragma unroll
+      for (int f = 0; f < NG; ++f) {
+        const int fg = F0 + f;
+        const double sum = acc[fg * ACC_HALF + ai] + ((double)H[f] - Hprev[f]);
+        finish_cell<T>(s, (size_t)fg * fs, leaf_at + i * 64, st[f].qy, u0v[f], sum,
+                       rot && fg >= 1 && fg <= 4, fg >= 1 && fg <= 4 ? src[fg - 1] : 0.0, dt,
+                       inv_dx);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NG; ++f) Hprev[f] = (double)H[f];
+  }
+}
+
+// W = waves per SIMD the register budget allows (1: up to 512 VGPRs, 2: 256).
+template <typename T, int NF, int W>
+__global__ void __launch_bounds__(128, W) k_step2(StepArgs s) {
+  static_assert(NF > NF_CORE, "the second wavefront needs passive species");
+  __shared__ __align__(16) double acc[NF * ACC_HALF];
+  __shared__ SpeedSlot<T> spd[2];
+  const GridArgs& g = s.g;
+  int bid = blockIdx.x;
+  if (s.remap) {
+    const int n = g.n_leaves, q = n >> 3, r = n & 7;
+    const int xcd = bid & 7, j = bid >> 3;
+    bid = xcd * q + min(xcd, r) + j;
+  }
+  const int leaf = s.leaf_base + bid;
+  if (leaf >= g.n_leaves) return;  // uniform over the workgroup
+  // the role of each wavefront alternates with the workgroup, so that the
+  // SIMDs the hardware deals consecutive wavefronts to carry core and
+  // species work in equal shares
+  const int wave = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) ^ (blockIdx.x & 1));
+  const int lane = threadIdx.x & 63;
+
+  LeafInfo li;
+  li.leaf = leaf;
+  const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
+  li.ix = c4.y;
+  li.iy = c4.z;
+  li.iz = c4.w;
+  li.blocks = g.base << c4.x;
+  const uint8_t* kd = g.kind + 27 * leaf;
+  const int32_t* nb = g.nbr + 27 * leaf;
+  const bool xlane = lane < 32;
+  FaceNbr fxy, fz;
+  fxy.klo = xlane ? (int)kd[12] : (int)kd[10];
+  fxy.ilo = xlane ? nb[12] : nb[10];
+  fxy.khi = xlane ? (int)kd[14] : (int)kd[16];
+  fxy.ihi = xlane ? nb[14] : nb[16];
+  fz.klo = kd[4];
+  fz.ilo = nb[4];
+  fz.khi = kd[22];
+  fz.ihi = nb[22];
+  fxy.rlo = fxy.rhi = fxy.flo = fxy.fhi = -1;
+  fz.rlo = fz.rhi = fz.flo = fz.fhi = -1;
+  if (g.reg) {
+    const int32_t* fsl = g.face_slot + 6 * leaf;
+    const int32_t* fin = g.fine_slot + 6 * leaf;
+    fxy.rlo = xlane ? fsl[0] : fsl[2];
+    fxy.rhi = xlane ? fsl[1] : fsl[3];
+    fxy.flo = xlane ? fin[0] : fin[2];
+    fxy.fhi = xlane ? fin[1] : fin[3];
+    fz.rlo = fsl[4];
+    fz.rhi = fsl[5];
+    fz.flo = fin[4];
+    fz.fhi = fin[5];
+  }
+  const double dt = *s.dt;
+  const double inv_dx = (double)(SUB * li.blocks);
+  Phys<T> ph;
+  ph.gamma = (T)g.gamma;
+  ph.gm1 = (T)(g.gamma - 1.0);
+  ph.eta1 = (T)g.eta1;
+
+  bool bad = false;
+  int sn = 0;  // stream steps taken: selects the hand-off slot
+  constexpr int NS = NF - NF_CORE;
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    if (wave == 0)
+      phase_xy_group<T, NF, 0, NF_CORE>(s, ph, li, fxy, acc, spd, sn, h, lane, bad);
+    else
+      phase_xy_group<T, NF, NF_CORE, NS>(s, ph, li, fxy, acc, spd, sn, h, lane, bad);
+    wave_lds_sync();
+    if (wave == 0)
+      phase_z_group<T, NF, 0, NF_CORE>(s, ph, li, fz, acc, spd, sn, h, lane, dt, inv_dx, bad);
+    else
+      phase_z_group<T, NF, NF_CORE, NS>(s, ph, li, fz, acc, spd, sn, h, lane, dt, inv_dx, bad);
     wave_lds_sync();
   }
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
@@ -1157,9 +1492,25 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1)
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
 }
 
+// Launch shape of the fused substep: waves per SIMD (register budget) and
+// wavefronts per leaf (1: k_step; 2: k_step2, species on the second).
+struct StepShape {
+  int waves_per_simd;
+  int waves_per_leaf;
+};
+
 template <typename T, int NF>
-inline hipError_t launch_step_nf(const StepArgs& a, int blocks, int waves, hipStream_t st) {
-  if (waves == 2)
+inline hipError_t launch_step_nf(const StepArgs& a, int blocks, StepShape sh, hipStream_t st) {
+  if constexpr (NF > NF_CORE) {
+    if (sh.waves_per_leaf == 2) {
+      if (sh.waves_per_simd == 2)
+        hipLaunchKernelGGL((k_step2<T, NF, 2>), dim3(blocks), dim3(128), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_step2<T, NF, 1>), dim3(blocks), dim3(128), 0, st, a);
+      return hipGetLastError();
+    }
+  }
+  if (sh.waves_per_simd == 2)
     hipLaunchKernelGGL((k_step<T, NF, 2>), dim3(blocks), dim3(64), 0, st, a);
   else
     hipLaunchKernelGGL((k_step<T, NF, 1>), dim3(blocks), dim3(64), 0, st, a);
@@ -1167,19 +1518,19 @@ inline hipError_t launch_step_nf(const StepArgs& a, int blocks, int waves, hipSt
 }
 
 template <typename T>
-inline hipError_t launch_step_t(const StepArgs& a, int blocks, int waves, hipStream_t st) {
+inline hipError_t launch_step_t(const StepArgs& a, int blocks, StepShape sh, hipStream_t st) {
   switch (a.g.nf) {
-    case 6: return launch_step_nf<T, 6>(a, blocks, waves, st);
-    case 7: return launch_step_nf<T, 7>(a, blocks, waves, st);
-    case 8: return launch_step_nf<T, 8>(a, blocks, waves, st);
-    case 9: return launch_step_nf<T, 9>(a, blocks, waves, st);
-    case 10: return launch_step_nf<T, 10>(a, blocks, waves, st);
-    case 11: return launch_step_nf<T, 11>(a, blocks, waves, st);
-    case 12: return launch_step_nf<T, 12>(a, blocks, waves, st);
-    case 13: return launch_step_nf<T, 13>(a, blocks, waves, st);
-    case 14: return launch_step_nf<T, 14>(a, blocks, waves, st);
-    case 15: return launch_step_nf<T, 15>(a, blocks, waves, st);
-    case 16: return launch_step_nf<T, 16>(a, blocks, waves, st);
+    case 6: return launch_step_nf<T, 6>(a, blocks, sh, st);
+    case 7: return launch_step_nf<T, 7>(a, blocks, sh, st);
+    case 8: return launch_step_nf<T, 8>(a, blocks, sh, st);
+    case 9: return launch_step_nf<T, 9>(a, blocks, sh, st);
+    case 10: return launch_step_nf<T, 10>(a, blocks, sh, st);
+    case 11: return launch_step_nf<T, 11>(a, blocks, sh, st);
+    case 12: return launch_step_nf<T, 12>(a, blocks, sh, st);
+    case 13: return launch_step_nf<T, 13>(a, blocks, sh, st);
+    case 14: return launch_step_nf<T, 14>(a, blocks, sh, st);
+    case 15: return launch_step_nf<T, 15>(a, blocks, sh, st);
+    case 16: return launch_step_nf<T, 16>(a, blocks, sh, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1218,8 +1569,8 @@ inline hipError_t launch_step3d_t(const StepArgs& a, int blocks, const T* G, hip
 }
 
 // One translation unit each.
-hipError_t launch_step_f64(const StepArgs& a, int blocks, int waves, hipStream_t st);
-hipError_t launch_step_f32(const StepArgs& a, int blocks, int waves, hipStream_t st);
+hipError_t launch_step_f64(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
+hipError_t launch_step_f32(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
 hipError_t launch_step3d(const StepArgs& a, int dtype, int blocks, const void* G, hipStream_t st);
 
 }  // namespace octohydro

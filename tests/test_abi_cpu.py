@@ -140,8 +140,14 @@ def test_launch_options_roundtrip_and_validation(hb):
             hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD, 2)
             assert hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD) == 2
             hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD, w0)
+        for nf in (7, 11, 16):
+            l0 = hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_LEAF)
+            hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_LEAF, 2)
+            assert hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_LEAF) == 2
+            hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_LEAF, l0)
+    # two wavefronts per leaf need passive species; 1 or 2 only
     for bad in ((0, 6, 1, 3), (0, 5, 1, 1), (2, 6, 1, 1), (0, 6, 9, 1), (1, 17, 2, 1),
-                (0, 6, 2, 5)):
+                (0, 6, 2, 5), (0, 6, 3, 2), (1, 11, 3, 3), (0, 11, 3, 0)):
         with pytest.raises(hb.HydroError) as e:
             hb.hydro_set_option(*bad)
         assert e.value.code == hb.HYDRO_E_ARG

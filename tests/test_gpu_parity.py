@@ -322,12 +322,15 @@ def test_turbulence_65k_leaves_sampled(env):
     _sampled_rk3(env, w, 32, 5)
 
 
-@pytest.mark.parametrize("nf", [7, 16])
+@pytest.mark.parametrize("nf", [7, 11, 16])
 @pytest.mark.parametrize("waves", [1, 2])
+@pytest.mark.parametrize("leaf_waves", [1, 2])
 @pytest.mark.parametrize("dtype", [0, 1])
-def test_every_register_budget_and_field_count(env, nf, waves, dtype):
-    """Both kernel register budgets, beyond the benchmark's field counts:
-    binary64 bit-exact against the oracle, binary32 within its rounding."""
+def test_every_register_budget_and_field_count(env, nf, waves, leaf_waves, dtype):
+    """Both kernel register budgets and both leaf shapes (one wavefront per
+    leaf, or two with the species on the second), beyond the benchmark's
+    field counts: binary64 bit-exact against the oracle, binary32 within its
+    rounding."""
     torch, hb = env
     w = inputs.blobs(base=2, max_level=2, threshold=0.5)
     rng = np.random.default_rng(nf)
@@ -335,7 +338,9 @@ def test_every_register_budget_and_field_count(env, nf, waves, dtype):
     w.U = np.ascontiguousarray(np.concatenate([w.U[:6], np.stack(extra)]) if nf > 6 else w.U[:6])
     grid, T, U = _setup(env, w, dtype=dtype)
     old = hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD)
+    old_lw = hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_LEAF)
     hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD, waves)
+    hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_LEAF, leaf_waves)
     try:
         dt_o = oracle.cfl_dt(T, w.U, 0.4)
         dt = torch.tensor([dt_o], dtype=torch.float64, device="cuda")
@@ -350,6 +355,7 @@ def test_every_register_budget_and_field_count(env, nf, waves, dtype):
             assert np.all(err < 1e-5), err
     finally:
         hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_SIMD, old)
+        hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_LEAF, old_lw)
 
 
 REFLUX_CASES = [("amr-base2-levels0-2", inputs.blobs(base=2, max_level=2, threshold=0.5)),
