@@ -91,6 +91,9 @@ extern "C" {
 #define HYDRO_FLAG_NODES_READY 2u /* node_state_dev (or ghost_tile_dev in the 3D
                                      mode) already holds this call's Uk: skip
                                      making it                                */
+#define HYDRO_FLAG_CFL_NEXT 4u    /* also leave the CFL minimum of Uout,
+                                     min over cells of dx / (max|v| + c), in
+                                     dt_dev[1] (dt_dev then holds 2 doubles) */
 
 /*
  * A batch of leaves (Sec. IV-C): host struct, device arrays.
@@ -165,6 +168,17 @@ typedef struct hydro_grid {
    * `dtype`, laid out like the output of hydro_fill_ghosts; required in that
    * mode, ignored otherwise.  Every 3D substep fills it from its Uk. */
   void* ghost_tile_dev;
+  /* Chained time steps (Sec. V-B-1: a substep takes part in computing the
+   * global time-step size): nonzero makes hydro_rk3_step and its graph take
+   * dt_dev as 2 doubles, read dt_dev[1] = the CFL minimum of Un (min over
+   * cells of dx / (max|v| + c)) that the previous step left there or that
+   * hydro_cfl_dt(grid, Un, 0.0, dt_dev + 1) made, set dt_dev[0] = cfl *
+   * dt_dev[1] (cfl > 0), and leave the minimum of Unext in dt_dev[1].  The
+   * last substep's kernel takes that minimum from the values it stores, so
+   * no pass over Un is needed (with the flux correction or the 3D
+   * reconstruction a pass over Unext does it).  The time steps are the same
+   * bits as with 0. */
+  int32_t cfl_epilogue;
 } hydro_grid;
 
 /*
@@ -243,6 +257,7 @@ int hydro_step_per_leaf(const hydro_grid* grid, const void* U0_dev, const void* 
  * Global time-step size (Sec. V-B-1): *dt_dev = cfl * min over all leaves and
  * interior cells of dx_L / (max(|v_x|,|v_y|,|v_z|) + c), in binary64 for
  * either dtype.  Exact min reduction: the result does not depend on order.
+ * cfl == 0 leaves the minimum itself (the input of a chained RK3 step).
  */
 int hydro_cfl_dt(const hydro_grid* grid, const void* U_dev, double cfl, double* dt_dev,
                  void* stream);
@@ -310,18 +325,26 @@ const char* hydro_last_error(void);
  * fastest; the Python binding applies its recorded choices at import.
  *   HYDRO_OPT_WAVES_PER_SIMD  1 or 2: register budget of the kernel (2 waves
  *                             per SIMD caps it at 256 VGPRs, which may spill)
- *   HYDRO_OPT_XCD_REMAP       0 or 1: give each XCD a contiguous leaf range
+ *   HYDRO_OPT_XCD_REMAP       which leaves each of the 8 XCDs works on:
+ *                             0 in launch order, 1 one contiguous range per
+ *                             XCD, c (a power of two in [2, 4096]) chunks
+ *                             of c consecutive leaves dealt in turn
  *   HYDRO_OPT_WAVES_PER_LEAF  1 or 2: wavefronts per leaf; with 2 (n_fields
  *                             > 6 only) the second wavefront of each leaf
  *                             evolves the passive species, taking each face's
  *                             velocities and signal speed from the first
  *                             through LDS (same bits, half the registers)
+ *   HYDRO_OPT_CFL_EPILOGUE    1 or 0: where a step that leaves the CFL
+ *                             minimum of its output (HYDRO_FLAG_CFL_NEXT,
+ *                             chained RK3 steps) takes it: in the substep
+ *                             kernel itself, or in a pass over the output
  * Every choice computes the same bits.  Options are process-wide and take effect at the next launch (a captured
  * graph keeps the kernel it was captured with).  Host only, thread-safe.
  */
 #define HYDRO_OPT_WAVES_PER_SIMD 1
 #define HYDRO_OPT_XCD_REMAP 2
 #define HYDRO_OPT_WAVES_PER_LEAF 3
+#define HYDRO_OPT_CFL_EPILOGUE 4
 int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t value);
 int hydro_get_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t* value);
 

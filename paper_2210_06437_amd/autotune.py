@@ -1,9 +1,17 @@
 """Autotuner for the launch options of the fused substep kernel.
 
-For each (dtype, n_fields) it times every choice of register budget (1 or 2
-wavefronts per SIMD) and XCD remap (off/on) on a workload of the benchmark's
-shape, through the C-ABI, and records the fastest in ``tuning.json`` next to
-this file.  ``binding.py`` applies the recorded choices when it is imported.
+For each (dtype, n_fields) it times every combination of
+  - register budget: 1 or 2 wavefronts per SIMD,
+  - leaf shape: 1 wavefront per leaf, or 2 (core fields and species on
+    separate wavefronts; only with passive species),
+  - XCD remap: leaves in launch order, one contiguous range per XCD, or
+    chunks of 64 or 512 consecutive leaves dealt to the XCDs in turn,
+on a workload of the benchmark's shape (the later-stage substep, which reads
+U0), through the C-ABI, and records the fastest in ``tuning.json`` next to
+this file with every measured variant; then, in the chosen shape, whether
+the last substep of a chained RK3 step takes the next CFL minimum in the
+kernel or in a pass over its output.  Every choice computes the same bits.
+``binding.py`` applies the recorded choices when it is imported.
 
 Run on the GPU:  python -m paper_2210_06437_amd.autotune [--quick]
 """
@@ -19,26 +27,28 @@ from . import binding as hb
 from . import inputs
 
 TUNING_PATH = hb.TUNING_PATH
+# XCD remap modes tried (see hydro_set_option)
+REMAPS = (0, 1, 64, 512)
 
 
-def _time_step(torch, grid, U, A, B, dt, reps):
+def _time_step(torch, grid, U, A, B, dt, reps, flags=0):
     # warm-up: loads the kernel and makes the restricted node copies of A,
     # which the timed calls reuse, so that only the substep kernel is timed
-    hb.hydro_step(grid, U, A, B, dt, 0.25)
+    hb.hydro_step(grid, U, A, B, dt, 0.25, flags=flags)
     torch.cuda.synchronize()
     best = float("inf")
     for _ in range(reps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        hb.hydro_step(grid, U, A, B, dt, 0.25, flags=hb.HYDRO_FLAG_NODES_READY)
+        hb.hydro_step(grid, U, A, B, dt, 0.25, flags=hb.HYDRO_FLAG_NODES_READY | flags)
         e1.record()
         torch.cuda.synchronize()
         best = min(best, e0.elapsed_time(e1))
     return best
 
 
-def tune_workload(torch, w, dtype, reps=3):
+def tune_workload(torch, w, dtype, reps=5):
     grid = hb.Grid(w.leaf_coord, w.base, w.nf, dtype)
     tdt = torch.float64 if dtype == hb.HYDRO_F64 else torch.float32
     U = torch.from_numpy(w.U).to("cuda").to(tdt).contiguous()
@@ -47,22 +57,43 @@ def tune_workload(torch, w, dtype, reps=3):
     hb.hydro_cfl_dt(grid, U, 0.4, dt)
     hb.hydro_step(grid, None, U, A, dt, 1.0)
     results = []
+    shapes = (1, 2) if w.nf > 6 else (1,)
     for waves in (1, 2):
-        for remap in (0, 1):
-            hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_SIMD, waves)
-            hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_XCD_REMAP, remap)
-            ms = _time_step(torch, grid, U, A, B, dt, reps)
-            results.append({"waves_per_simd": waves, "xcd_remap": remap, "ms": ms})
-            print(f"[autotune] dtype={dtype} nf={w.nf} waves={waves} remap={remap}: {ms:.3f} ms",
-                  file=sys.stderr, flush=True)
+        for leaf_waves in shapes:
+            for remap in REMAPS:
+                hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_SIMD, waves)
+                hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, leaf_waves)
+                hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_XCD_REMAP, remap)
+                ms = _time_step(torch, grid, U, A, B, dt, reps)
+                results.append({"waves_per_simd": waves, "waves_per_leaf": leaf_waves,
+                                "xcd_remap": remap, "ms": ms})
+                print(f"[autotune] dtype={dtype} nf={w.nf} waves/SIMD={waves} "
+                      f"waves/leaf={leaf_waves} remap={remap}: {ms:.3f} ms",
+                      file=sys.stderr, flush=True)
     best = min(results, key=lambda r: r["ms"])
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_SIMD, best["waves_per_simd"])
+    hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, best["waves_per_leaf"])
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_XCD_REMAP, best["xcd_remap"])
+    # the last substep of a chained RK3 step in the chosen shape: the CFL
+    # minimum of its output taken in the kernel, or in a pass after it
+    dt2 = torch.zeros(2, dtype=torch.float64, device="cuda")
+    dt2[0] = dt[0]
+    cfl = []
+    for epi in (1, 0):
+        hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_CFL_EPILOGUE, epi)
+        ms = _time_step(torch, grid, U, A, B, dt2, reps, hb.HYDRO_FLAG_CFL_NEXT)
+        cfl.append({"cfl_epilogue": epi, "ms": ms})
+        print(f"[autotune] dtype={dtype} nf={w.nf} last substep, CFL "
+              f"{'in the kernel' if epi else 'in a pass'}: {ms:.3f} ms",
+              file=sys.stderr, flush=True)
+    epi = min(cfl, key=lambda r: r["ms"])["cfl_epilogue"]
+    hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_CFL_EPILOGUE, epi)
     del U, A, B
     torch.cuda.empty_cache()
     return {"dtype": dtype, "n_fields": w.nf, "waves_per_simd": best["waves_per_simd"],
-            "xcd_remap": best["xcd_remap"], "ms": best["ms"], "workload": w.name,
-            "leaves": w.n_leaves, "all": results}
+            "waves_per_leaf": best["waves_per_leaf"], "xcd_remap": best["xcd_remap"],
+            "cfl_epilogue": epi, "ms": best["ms"], "workload": w.name, "leaves": w.n_leaves,
+            "all": results, "last_substep": cfl}
 
 
 def main():
@@ -84,7 +115,8 @@ def main():
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps({"wrote": args.out, "choices": [
-        {k: e[k] for k in ("dtype", "n_fields", "waves_per_simd", "xcd_remap", "ms")}
+        {k: e[k] for k in ("dtype", "n_fields", "waves_per_simd", "waves_per_leaf", "xcd_remap",
+                           "cfl_epilogue", "ms")}
         for e in entries]}))
 
 

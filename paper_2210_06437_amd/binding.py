@@ -29,6 +29,7 @@ HYDRO_F64, HYDRO_F32 = 0, 1
 HYDRO_SAME_LEAF, HYDRO_SAME_REFINED, HYDRO_COARSER_LEAF = 0, 1, 2
 HYDRO_FLAG_VALIDATE = 1
 HYDRO_FLAG_NODES_READY = 2
+HYDRO_FLAG_CFL_NEXT = 4
 HYDRO_RECON_AXIS, HYDRO_RECON_3D = 0, 1
 HYDRO_MAX_LEAVES = 1048575
 HYDRO_STATUS_UNPHYSICAL, HYDRO_STATUS_TABLE = 1, 2
@@ -41,6 +42,7 @@ EXPORTS = [
     "hydro_totals_noalloc",
 ]
 HYDRO_OPT_WAVES_PER_SIMD, HYDRO_OPT_XCD_REMAP, HYDRO_OPT_WAVES_PER_LEAF = 1, 2, 3
+HYDRO_OPT_CFL_EPILOGUE = 4
 
 
 class HydroError(RuntimeError):
@@ -73,6 +75,7 @@ class hydro_grid(ctypes.Structure):
         ("omega", ctypes.c_double),
         ("node_state_dev", ctypes.c_void_p),
         ("ghost_tile_dev", ctypes.c_void_p),
+        ("cfl_epilogue", ctypes.c_int32),
     ]
 
 
@@ -130,6 +133,8 @@ def apply_tuning(path: str = TUNING_PATH) -> int:
         _lib.hydro_set_option(int(e["dtype"]), int(e["n_fields"]), 2, int(e["xcd_remap"]))
         _lib.hydro_set_option(int(e["dtype"]), int(e["n_fields"]), 3,
                               int(e.get("waves_per_leaf", 1)))
+        _lib.hydro_set_option(int(e["dtype"]), int(e["n_fields"]), 4,
+                              int(e.get("cfl_epilogue", 1)))
         n += 1
     return n
 
@@ -210,11 +215,12 @@ class Grid:
     """A leaf batch resident on the GPU: the table in device memory plus the
     hydro_grid struct that points at it.  reflux=True also builds the
     flux-register tables and scratch, which turns on the coarse-fine flux
-    correction."""
+    correction.  cfl_epilogue=True chains the RK3 steps' time steps (dt of
+    2 doubles; see hydro_grid.cfl_epilogue)."""
 
     def __init__(self, leaf_coord, base, n_fields, dtype=HYDRO_F64, gamma=5.0 / 3.0,
                  eta1=1e-3, device="cuda", reflux=False, omega=0.0,
-                 reconstruction=HYDRO_RECON_AXIS):
+                 reconstruction=HYDRO_RECON_AXIS, cfl_epilogue=False):
         coord = np.ascontiguousarray(leaf_coord, dtype=np.int32)
         nbr, kind, kids = hydro_build_table(coord, base)
         self.host_nbr, self.host_kind, self.host_children = nbr, kind, kids
@@ -235,7 +241,8 @@ class Grid:
             leaf_coord_dev=self.coord.data_ptr(),
             nbr_dev=self.nbr.data_ptr(), nbr_kind_dev=self.kind.data_ptr(),
             children_dev=self.children.data_ptr(), status_dev=self.status.data_ptr(),
-            gamma=float(gamma), dual_energy_eta1=float(eta1), omega=float(omega))
+            gamma=float(gamma), dual_energy_eta1=float(eta1), omega=float(omega),
+            cfl_epilogue=int(bool(cfl_epilogue)))
         # scratch of the reconstruction: materialised ghosted tiles (3D), or
         # the restricted copies of the refined blocks
         if reconstruction == HYDRO_RECON_3D:

@@ -94,10 +94,14 @@ __global__ void k_dt_final(double* dt, double cfl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dt = cfl * *dt;
 }
 
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
+// Time step of a chained RK3 step: dt[0] = cfl * dt[1], the CFL minimum of
+// the step's input left by the previous step; dt[1] = +inf, ready for the
+// minimum of the step's output.
+__global__ void k_dt_take(double* dt, double cfl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    dt[0] = cfl * dt[1];
+    *reinterpret_cast<unsigned long long*>(dt + 1) = 0x7FF0000000000000ull;
+  }
 }
 
 template <typename T>
@@ -359,6 +363,7 @@ struct Options {
   int waves_per_simd = 1;
   int xcd_remap = 1;
   int waves_per_leaf = 1;
+  int cfl_epilogue = 1;
 };
 static Options g_opts[2][17];
 static std::mutex g_opts_mu;
@@ -368,10 +373,22 @@ static Options get_options(int dtype, int nf) {
   return g_opts[dtype][nf];
 }
 
+// Whether the step kernel itself leaves the CFL minimum of its output: the
+// axis reconstruction without the flux correction (the correction changes
+// cells after the kernel; the 3D step has no epilogue) when the launch
+// option asks for it; else a pass of k_cfl over the output does it.
+static bool cfl_in_kernel(const hydro_grid* gr, const StepArgs& a) {
+  return gr->reconstruction == HYDRO_RECON_AXIS && a.g.reg == nullptr &&
+         get_options(gr->dtype, gr->n_fields).cfl_epilogue != 0;
+}
+
 static hipError_t launch_step(StepArgs a, int dtype, int blocks, hipStream_t st) {
   const Options o = get_options(dtype, a.g.nf);
   if (a.remap) a.remap = o.xcd_remap;
   const StepShape sh{o.waves_per_simd, o.waves_per_leaf};
+  if (a.dt_next)
+    return dtype == HYDRO_F64 ? launch_step_f64_cfl(a, blocks, sh, st)
+                              : launch_step_f32_cfl(a, blocks, sh, st);
   return dtype == HYDRO_F64 ? launch_step_f64(a, blocks, sh, st)
                             : launch_step_f32(a, blocks, sh, st);
 }
@@ -398,7 +415,7 @@ static int step_common(const hydro_grid* gr, const void* U0, const void* Uk, voi
   if (!Uk || !Uout || !dt) return fail(HYDRO_E_ARG, "%s: Uk, Uout and dt must be set", fn);
   if (Uout == Uk || (U0 && Uout == U0))
     return fail(HYDRO_E_ARG, "%s: Uout may not alias an input", fn);
-  if (flags & ~(HYDRO_FLAG_VALIDATE | HYDRO_FLAG_NODES_READY))
+  if (flags & ~(HYDRO_FLAG_VALIDATE | HYDRO_FLAG_NODES_READY | HYDRO_FLAG_CFL_NEXT))
     return fail(HYDRO_E_ARG, "%s: unknown flags", fn);
   if (gr->reconstruction == HYDRO_RECON_3D) {
     if (!gr->ghost_tile_dev)
@@ -422,9 +439,11 @@ static int step_common(const hydro_grid* gr, const void* U0, const void* Uk, voi
   a.beta = beta;
   a.leaf_base = 0;
   a.remap = 1;
+  a.dt_next = nullptr;
   return HYDRO_OK;
 }
 
+// *dt = cfl * (CFL minimum of U); with cfl == 0 the raw minimum is left.
 static int cfl_launch(const hydro_grid* gr, const void* U, double cfl, double* dt, hipStream_t st) {
   GridArgs g = grid_args(gr);
   hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(64), 0, st, dt);
@@ -437,10 +456,14 @@ static int cfl_launch(const hydro_grid* gr, const void* U, double cfl, double* d
     hipLaunchKernelGGL(k_cfl<float>, dim3(blocks), dim3(256), 0, st, g,
                        static_cast<const float*>(U), dt);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(64), 0, st, dt, cfl);
-  HIP_TRY(hipGetLastError());
+  if (cfl != 0.0) {
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(64), 0, st, dt, cfl);
+    HIP_TRY(hipGetLastError());
+  }
   return HYDRO_OK;
 }
+
+
 
 // One substep on `st`: the pre-pass of the reconstruction (restricted node
 // copies, or the materialised tiles of the 3D mode), the step kernel over
@@ -470,7 +493,15 @@ static int rk3_launch(const hydro_grid* gr, const void* Un, void* W1, void* W2, 
   StepArgs a;
   rc = step_common(gr, nullptr, Un, W1, dt, 1.0, 0, "hydro_rk3_step", a);
   if (rc) return rc;
-  if (cfl > 0.0) {
+  const bool chained = gr->cfl_epilogue != 0;
+  if (chained) {
+    // dt[0] from the minimum of Un that the previous step left in dt[1]
+    if (cfl > 0.0)
+      hipLaunchKernelGGL(k_dt_take, dim3(1), dim3(64), 0, st, dt, cfl);
+    else
+      hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(64), 0, st, dt + 1);
+    HIP_TRY(hipGetLastError());
+  } else if (cfl > 0.0) {
     rc = cfl_launch(gr, Un, cfl, dt, st);
     if (rc) return rc;
   }
@@ -485,8 +516,10 @@ static int rk3_launch(const hydro_grid* gr, const void* Un, void* W1, void* W2, 
   a.Uk = W2;
   a.Uout = Unext;
   a.beta = 2.0 / 3.0;
+  if (chained && cfl_in_kernel(gr, a)) a.dt_next = dt + 1;
   if ((rc = substep_kernels(gr, a, gr->n_leaves, true, st))) return rc;
   if ((rc = reflux_launch(gr, a, st))) return rc;
+  if (chained && !a.dt_next) return cfl_launch(gr, Unext, 0.0, dt + 1, st);
   return HYDRO_OK;
 }
 
@@ -584,8 +617,15 @@ int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t va
       o.waves_per_simd = value;
       return HYDRO_OK;
     case HYDRO_OPT_XCD_REMAP:
-      if (value != 0 && value != 1) return fail(HYDRO_E_ARG, "hydro_set_option: remap is 0 or 1");
+      if (value < 0 || value > 4096 || (value >= 2 && (value & (value - 1))))
+        return fail(HYDRO_E_ARG,
+                    "hydro_set_option: remap is 0, 1 or a power of two in [2, 4096]");
       o.xcd_remap = value;
+      return HYDRO_OK;
+    case HYDRO_OPT_CFL_EPILOGUE:
+      if (value != 0 && value != 1)
+        return fail(HYDRO_E_ARG, "hydro_set_option: CFL epilogue is 0 or 1");
+      o.cfl_epilogue = value;
       return HYDRO_OK;
     case HYDRO_OPT_WAVES_PER_LEAF:
       if (value != 1 && value != 2)
@@ -607,6 +647,7 @@ int hydro_get_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t* v
   if (option == HYDRO_OPT_WAVES_PER_SIMD) *value = o.waves_per_simd;
   else if (option == HYDRO_OPT_XCD_REMAP) *value = o.xcd_remap;
   else if (option == HYDRO_OPT_WAVES_PER_LEAF) *value = o.waves_per_leaf;
+  else if (option == HYDRO_OPT_CFL_EPILOGUE) *value = o.cfl_epilogue;
   else return fail(HYDRO_E_ARG, "hydro_get_option: unknown option %d", option);
   return HYDRO_OK;
 }
@@ -633,9 +674,19 @@ int hydro_step(const hydro_grid* gr, const void* U0, const void* Uk, void* Uout,
     rc = validate_table(gr, st);
     if (rc) return rc;
   }
+  const bool cfl_next = (flags & HYDRO_FLAG_CFL_NEXT) != 0;
+  if (cfl_next) {
+    if (cfl_in_kernel(gr, a)) {
+      hipLaunchKernelGGL(k_dt_init, dim3(1), dim3(64), 0, st, const_cast<double*>(dt) + 1);
+      HIP_TRY(hipGetLastError());
+      a.dt_next = const_cast<double*>(dt) + 1;
+    }
+  }
   if ((rc = substep_kernels(gr, a, gr->n_leaves, !(flags & HYDRO_FLAG_NODES_READY), st)))
     return rc;
-  return reflux_launch(gr, a, st);
+  if ((rc = reflux_launch(gr, a, st))) return rc;
+  if (cfl_next && !a.dt_next) return cfl_launch(gr, Uout, 0.0, const_cast<double*>(dt) + 1, st);
+  return HYDRO_OK;
 }
 
 int hydro_step_per_leaf(const hydro_grid* gr, const void* U0, const void* Uk, void* Uout,
@@ -691,7 +742,7 @@ int hydro_cfl_dt(const hydro_grid* gr, const void* U, double cfl, double* dt, vo
   int rc = check_grid(gr, "hydro_cfl_dt");
   if (rc) return rc;
   if (!U || !dt) return fail(HYDRO_E_ARG, "hydro_cfl_dt: U and dt must be set");
-  if (!(cfl > 0.0)) return fail(HYDRO_E_ARG, "hydro_cfl_dt: cfl must be positive");
+  if (!(cfl >= 0.0)) return fail(HYDRO_E_ARG, "hydro_cfl_dt: cfl must not be negative");
   return cfl_launch(gr, U, cfl, dt, static_cast<hipStream_t>(stream));
 }
 

@@ -267,6 +267,28 @@ __device__ __forceinline__ bool eos(const Phys<T>& ph, T rho, T sx, T sy, T sz, 
 // Fused substep kernel
 // ---------------------------------------------------------------------------
 
+// Leaf of workgroup `bid` under the XCD remap mode (the hardware deals
+// consecutive workgroups to the 8 XCDs in turn, so workgroup b runs on XCD
+// b % 8 as its (b / 8)-th): 0 keeps b; 1 gives each XCD one contiguous
+// range of leaves; c >= 2 deals chunks of c consecutive leaves to the XCDs
+// in turn (leaves past the last whole round of 8 chunks keep b).  Leaves
+// are stored in Morton order, so either keeps the leaves an XCD works on at
+// once close in space and their halos in that XCD's L2.
+__device__ __forceinline__ int leaf_of_block(int bid, int n, int remap) {
+  if (remap == 1) {
+    const int q = n >> 3, r = n & 7;
+    const int xcd = bid & 7, j = bid >> 3;
+    return xcd * q + min(xcd, r) + j;
+  }
+  if (remap >= 2) {
+    const int round = 8 * remap;
+    if (bid >= (n / round) * round) return bid;
+    const int xcd = bid & 7, j = bid >> 3;
+    return ((j / remap) * 8 + xcd) * remap + j % remap;
+  }
+  return bid;
+}
+
 struct StepArgs {
   GridArgs g;
   const void* U0;
@@ -275,8 +297,46 @@ struct StepArgs {
   const double* dt;
   double beta;
   int32_t leaf_base;  // first leaf (per-leaf launches); 0 for the batch
-  int32_t remap;      // 1: spread contiguous leaf ranges over the 8 XCDs
+  int32_t remap;      // XCD remap mode of leaf_of_block
+  // CFL epilogue: when set, the kernel also takes the minimum over its cells
+  // of dx / (max|v| + c) of the values it stores (Sec. V-B-1: the substep
+  // takes part in the global time-step size) into *dt_next (a binary64
+  // whose bit pattern is reduced with an unsigned 64-bit atomic min)
+  double* dt_next;
 };
+
+// Per-cell CFL quantity dx / (max(|v_x|, |v_y|, |v_z|) + c) of a stored
+// state (rho, s, E, tau as stored, in binary64), evaluated operation by
+// operation as the time-step pass hydro_cfl_dt does.
+template <typename T>
+__device__ __forceinline__ double cfl_quantity(const GridArgs& g, const T (&cv)[NF_CORE],
+                                               double dx) {
+  const double rho = (double)cv[0], sx = (double)cv[1], sy = (double)cv[2];
+  const double sz = (double)cv[3], E = (double)cv[4];
+  const double rinv = 1.0 / rho;
+  const double ss = (sx * sx + sy * sy) + sz * sz;
+  double ei = E - 0.5 * ss * rinv;
+  if (ei < g.eta1 * E) ei = tau_energy((double)cv[5], g.gamma);
+  const double p = (g.gamma - 1.0) * ei;
+  const double c = sqrt(g.gamma * p * rinv);
+  const double vmax = fmax(fmax(fabs(sx * rinv), fabs(sy * rinv)), fabs(sz * rinv));
+  return dx / (vmax + c);
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Wavefront minimum of a positive binary64 into *out by an unsigned 64-bit
+// atomic min on its bit pattern (positive doubles order like their bits).
+__device__ __forceinline__ void atomic_min_positive(double* out, double v, int lane) {
+  v = wave_min(v);
+  if (lane == 0)
+    atomicMin(reinterpret_cast<unsigned long long*>(out),
+              (unsigned long long)__double_as_longlong(v));
+}
 
 // Per-leaf constants.  Neighbour kinds and ids of the six face neighbours are
 // handed to the phases as plain values (the phase picks its axis once), so
@@ -446,39 +506,32 @@ __device__ __forceinline__ float bload_once(float, const FieldView& v, uint32_t 
 struct Sources {
   Rsrc uk, rn;
   uint32_t uk_fs, rn_fs;
-  const char* uk_ptr;  // the same two arrays as plain addresses
-  const char* rn_ptr;
 };
 
 __device__ __forceinline__ Sources make_sources(const void* Uk, const void* rstate, int nf,
                                                 uint32_t uk_fs, uint32_t rn_fs) {
   return Sources{state_rsrc(Uk, (uint32_t)nf * uk_fs),
-                 state_rsrc(rstate, rstate ? (uint32_t)nf * rn_fs : 0u), uk_fs, rn_fs,
-                 static_cast<const char*>(Uk), static_cast<const char*>(rstate)};
-}
-
-// One field value at byte offset o of a field array starting at p.
-template <typename T>
-__device__ __forceinline__ T gload(const char* p, uint32_t o) {
-  return *reinterpret_cast<const T*>(p + o);
+                 state_rsrc(rstate, rstate ? (uint32_t)nf * rn_fs : 0u), uk_fs, rn_fs};
 }
 
 // The values of a stream position in all NF fields.  Where some lane of the
-// wave reads a node copy, the lanes read from two arrays: each lane forms
-// the address of its own value in its own array (a 64-bit base and field
-// stride picked once per position) and every field is one plain load, all
-// issued before any is used.  (A buffer load takes its array from scalar
-// registers, so reading both arrays with buffer loads takes two loads and a
-// select per field, which the compiler serialised with a full memory wait
-// per field: 11 memory latencies per such position.)  The test is made
-// once per position, not once per field.
+// wave reads a node copy, the lanes read from two arrays: the lanes of each
+// array load under their own execution mask into the same registers, all
+// fields issued before any is used, with no select.  (Two loads per field,
+// one of them past the end of its array, and a select took two registers
+// per field and made the compiler serialise the loads with a full memory
+// wait per field: 11 memory latencies per such position.)  The test is
+// made once per position, not once per field.
 template <typename T, int NF>
 __device__ __forceinline__ void load_position(const Sources& S, const Src& s, T (&q)[NF]) {
   if (s.any_ref) {
-    const char* base = (s.ref ? S.rn_ptr : S.uk_ptr) + s.o;
-    const uint32_t fsb = s.ref ? S.rn_fs : S.uk_fs;
+    if (s.ref) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) q[f] = gload<T>(base, f * fsb);
+      for (int f = 0; f < NF; ++f) q[f] = bload(T(), FieldView{S.rn, f * S.rn_fs}, s.o);
+    } else {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) q[f] = bload(T(), FieldView{S.uk, f * S.uk_fs}, s.o);
+    }
   } else {
 #pragma unroll
     for (int f = 0; f < NF; ++f) q[f] = bload(T(), FieldView{S.uk, f * S.uk_fs}, s.o);
@@ -522,9 +575,9 @@ __device__ __forceinline__ void core_flux(const Phys<T>& ph, int d, const T (&UL
 // t (first stage) or U0 + beta (t - U0); u0 is the cell's U0 value, loaded
 // by the caller ahead of time.
 template <typename T>
-__device__ __forceinline__ void finish_cell(const StepArgs& s, size_t fbase, uint32_t cell, T uk,
-                                            T u0, double sum, bool has_src, double src,
-                                            double dt, double inv_dx) {
+__device__ __forceinline__ T finish_cell(const StepArgs& s, size_t fbase, uint32_t cell, T uk,
+                                         T u0, double sum, bool has_src, double src, double dt,
+                                         double inv_dx) {
   double lrate = -sum * inv_dx;
   if (has_src) lrate = lrate + src;
   const double t = (double)uk + dt * lrate;
@@ -537,6 +590,7 @@ __device__ __forceinline__ void finish_cell(const StepArgs& s, size_t fbase, uin
   }
   // the result is not read again by this kernel: keep it out of the caches
   __builtin_nontemporal_store((T)out, static_cast<T*>(s.Uout) + fbase + cell);
+  return (T)out;
 }
 
 // Scheduling fence between the per-field reconstructions of a stream step:
@@ -677,10 +731,11 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
 // Phase Z of half h: lane (x, y) streams its z-pencil over stream positions
 // [4h, 4h+10), which yields the z-faces of cells z in [4h, 4h+4), adds dHz
 // to the accumulator and finishes those cells.
-template <typename T, int NF>
+template <typename T, int NF, bool CFL>
 __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
                                         const FaceNbr& fn, const double* __restrict__ acc, int h,
-                                        int lane, double dt, double inv_dx, bool& bad) {
+                                        int lane, double dt, double inv_dx, bool& bad,
+                                        double& cflmin) {
   const GridArgs& g = s.g;
   const size_t fs = (size_t)g.n_leaves * CELLS;
   const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
@@ -738,12 +793,16 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
         src[1] = rho * om2 * ry - tw * sx;
         src[3] = om2 * (sx * rx + sy * ry);
       }
+      T cv[NF_CORE];
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
         const double sum = acc[f * ACC_HALF + ai] + ((double)H[f] - Hprev[f]);
-        finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, st[f].qy, u0v[f], sum,
-                       rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+        const T o = finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, st[f].qy, u0v[f], sum,
+                                   rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0,
+                                   dt, inv_dx);
+        if (f < NF_CORE) cv[f] = o;
       }
+      if constexpr (CFL) cflmin = fmin(cflmin, cfl_quantity<T>(g, cv, 1.0 / inv_dx));
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) Hprev[f] = (double)H[f];
@@ -751,19 +810,13 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
 }
 
 // W = register budget: W waves per SIMD (1: up to 512 VGPRs, 2: up to 256).
-template <typename T, int NF, int W>
+// CFL: the instantiation with the CFL epilogue (s.dt_next set), a separate
+// kernel so that the others keep its registers.
+template <typename T, int NF, int W, bool CFL>
 __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
   __shared__ __align__(16) double acc[NF * ACC_HALF];
   const GridArgs& g = s.g;
-  int bid = blockIdx.x;
-  if (s.remap) {
-    // contiguous (Morton-ordered) leaf ranges per XCD: blocks are dealt to
-    // the 8 XCDs round-robin, so block b runs on XCD b % 8
-    const int n = g.n_leaves, q = n >> 3, r = n & 7;
-    const int xcd = bid & 7, j = bid >> 3;
-    bid = xcd * q + min(xcd, r) + j;
-  }
-  const int leaf = s.leaf_base + bid;
+  const int leaf = s.leaf_base + leaf_of_block(blockIdx.x, g.n_leaves, s.remap);
   if (leaf >= g.n_leaves) return;
   const int lane = threadIdx.x;
 
@@ -810,13 +863,15 @@ __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
   ph.eta1 = (T)g.eta1;
 
   bool bad = false;
+  double cflmin = INFINITY;
 #pragma unroll 1
   for (int h = 0; h < 2; ++h) {
     phase_xy<T, NF>(s, ph, li, fxy, acc, h, lane, bad);
     wave_lds_sync();
-    phase_z<T, NF>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad);
+    phase_z<T, NF, CFL>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad, cflmin);
     wave_lds_sync();
   }
+  if constexpr (CFL) atomic_min_positive(s.dt_next, cflmin, lane);
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
 }
 
@@ -845,10 +900,13 @@ struct SpeedSlot {
 template <typename T, int F0, int NG>
 __device__ __forceinline__ void load_group(const Sources& S, const Src& s, T (&q)[NG]) {
   if (s.any_ref) {
-    const char* base = (s.ref ? S.rn_ptr : S.uk_ptr) + s.o;
-    const uint32_t fsb = s.ref ? S.rn_fs : S.uk_fs;
+    if (s.ref) {
 #pragma unroll
-    for (int i = 0; i < NG; ++i) q[i] = gload<T>(base, (F0 + i) * fsb);
+      for (int i = 0; i < NG; ++i) q[i] = bload(T(), FieldView{S.rn, (F0 + i) * S.rn_fs}, s.o);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NG; ++i) q[i] = bload(T(), FieldView{S.uk, (F0 + i) * S.uk_fs}, s.o);
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < NG; ++i) q[i] = bload(T(), FieldView{S.uk, (F0 + i) * S.uk_fs}, s.o);
@@ -990,12 +1048,13 @@ __device__ __forceinline__ void phase_xy_group(const StepArgs& s, const Phys<T>&
 
 // Phase Z of half h for one field group (see phase_z); the core group adds
 // the rotating-frame sources.
-template <typename T, int NF, int F0, int NG>
+template <typename T, int NF, int F0, int NG, bool CFL>
 __device__ __forceinline__ void phase_z_group(const StepArgs& s, const Phys<T>& ph,
                                               const LeafInfo& li, const FaceNbr& fn,
                                               const double* __restrict__ acc,
                                               SpeedSlot<T>* __restrict__ spd, int& sn, int h,
-                                              int lane, double dt, double inv_dx, bool& bad) {
+                                              int lane, double dt, double inv_dx, bool& bad,
+                                              double& cflmin) {
   const GridArgs& g = s.g;
   const size_t fs = (size_t)g.n_leaves * CELLS;
   const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
@@ -1052,34 +1111,32 @@ __device__ __forceinline__ void phase_z_group(const StepArgs& s, const Phys<T>& 
         src[1] = rho * om2 * ry - tw * sx;
         src[3] = om2 * (sx * rx + sy * ry);
       }
+      T cv[NF_CORE];
 #pragma unroll
       for (int f = 0; f < NG; ++f) {
         const int fg = F0 + f;
         const double sum = acc[fg * ACC_HALF + ai] + ((double)H[f] - Hprev[f]);
-        finish_cell<T>(s, (size_t)fg * fs, leaf_at + i * 64, st[f].qy, u0v[f], sum,
-                       rot && fg >= 1 && fg <= 4, fg >= 1 && fg <= 4 ? src[fg - 1] : 0.0, dt,
-                       inv_dx);
+        const T o = finish_cell<T>(s, (size_t)fg * fs, leaf_at + i * 64, st[f].qy, u0v[f], sum,
+                                   rot && fg >= 1 && fg <= 4,
+                                   fg >= 1 && fg <= 4 ? src[fg - 1] : 0.0, dt, inv_dx);
+        if (F0 == 0 && f < NF_CORE) cv[f] = o;
       }
+      if constexpr (CFL && F0 == 0) cflmin = fmin(cflmin, cfl_quantity<T>(g, cv, 1.0 / inv_dx));
     }
 #pragma unroll
     for (int f = 0; f < NG; ++f) Hprev[f] = (double)H[f];
   }
 }
 
-// W = waves per SIMD the register budget allows (1: up to 512 VGPRs, 2: 256).
-template <typename T, int NF, int W>
+// W = waves per SIMD the register budget allows (1: up to 512 VGPRs, 2: 256);
+// CFL as for k_step.
+template <typename T, int NF, int W, bool CFL>
 __global__ void __launch_bounds__(128, W) k_step2(StepArgs s) {
   static_assert(NF > NF_CORE, "the second wavefront needs passive species");
   __shared__ __align__(16) double acc[NF * ACC_HALF];
   __shared__ SpeedSlot<T> spd[2];
   const GridArgs& g = s.g;
-  int bid = blockIdx.x;
-  if (s.remap) {
-    const int n = g.n_leaves, q = n >> 3, r = n & 7;
-    const int xcd = bid & 7, j = bid >> 3;
-    bid = xcd * q + min(xcd, r) + j;
-  }
-  const int leaf = s.leaf_base + bid;
+  const int leaf = s.leaf_base + leaf_of_block(blockIdx.x, g.n_leaves, s.remap);
   if (leaf >= g.n_leaves) return;  // uniform over the workgroup
   // the role of each wavefront alternates with the workgroup, so that the
   // SIMDs the hardware deals consecutive wavefronts to carry core and
@@ -1128,6 +1185,7 @@ __global__ void __launch_bounds__(128, W) k_step2(StepArgs s) {
   ph.eta1 = (T)g.eta1;
 
   bool bad = false;
+  double cflmin = INFINITY;
   int sn = 0;  // stream steps taken: selects the hand-off slot
   constexpr int NS = NF - NF_CORE;
 #pragma unroll 1
@@ -1138,10 +1196,15 @@ __global__ void __launch_bounds__(128, W) k_step2(StepArgs s) {
       phase_xy_group<T, NF, NF_CORE, NS>(s, ph, li, fxy, acc, spd, sn, h, lane, bad);
     wave_lds_sync();
     if (wave == 0)
-      phase_z_group<T, NF, 0, NF_CORE>(s, ph, li, fz, acc, spd, sn, h, lane, dt, inv_dx, bad);
+      phase_z_group<T, NF, 0, NF_CORE, CFL>(s, ph, li, fz, acc, spd, sn, h, lane, dt, inv_dx,
+                                            bad, cflmin);
     else
-      phase_z_group<T, NF, NF_CORE, NS>(s, ph, li, fz, acc, spd, sn, h, lane, dt, inv_dx, bad);
+      phase_z_group<T, NF, NF_CORE, NS, CFL>(s, ph, li, fz, acc, spd, sn, h, lane, dt, inv_dx,
+                                             bad, cflmin);
     wave_lds_sync();
+  }
+  if constexpr (CFL) {
+    if (wave == 0) atomic_min_positive(s.dt_next, cflmin, lane);
   }
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
 }
@@ -1499,38 +1562,40 @@ struct StepShape {
   int waves_per_leaf;
 };
 
-template <typename T, int NF>
+template <typename T, int NF, bool CFL>
 inline hipError_t launch_step_nf(const StepArgs& a, int blocks, StepShape sh, hipStream_t st) {
   if constexpr (NF > NF_CORE) {
     if (sh.waves_per_leaf == 2) {
       if (sh.waves_per_simd == 2)
-        hipLaunchKernelGGL((k_step2<T, NF, 2>), dim3(blocks), dim3(128), 0, st, a);
+        hipLaunchKernelGGL((k_step2<T, NF, 2, CFL>), dim3(blocks), dim3(128), 0, st, a);
       else
-        hipLaunchKernelGGL((k_step2<T, NF, 1>), dim3(blocks), dim3(128), 0, st, a);
+        hipLaunchKernelGGL((k_step2<T, NF, 1, CFL>), dim3(blocks), dim3(128), 0, st, a);
       return hipGetLastError();
     }
   }
   if (sh.waves_per_simd == 2)
-    hipLaunchKernelGGL((k_step<T, NF, 2>), dim3(blocks), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_step<T, NF, 2, CFL>), dim3(blocks), dim3(64), 0, st, a);
   else
-    hipLaunchKernelGGL((k_step<T, NF, 1>), dim3(blocks), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_step<T, NF, 1, CFL>), dim3(blocks), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
-template <typename T>
+// Launch of the fused substep for any field count; CFL selects the
+// instantiations with the CFL epilogue (a.dt_next set).
+template <typename T, bool CFL>
 inline hipError_t launch_step_t(const StepArgs& a, int blocks, StepShape sh, hipStream_t st) {
   switch (a.g.nf) {
-    case 6: return launch_step_nf<T, 6>(a, blocks, sh, st);
-    case 7: return launch_step_nf<T, 7>(a, blocks, sh, st);
-    case 8: return launch_step_nf<T, 8>(a, blocks, sh, st);
-    case 9: return launch_step_nf<T, 9>(a, blocks, sh, st);
-    case 10: return launch_step_nf<T, 10>(a, blocks, sh, st);
-    case 11: return launch_step_nf<T, 11>(a, blocks, sh, st);
-    case 12: return launch_step_nf<T, 12>(a, blocks, sh, st);
-    case 13: return launch_step_nf<T, 13>(a, blocks, sh, st);
-    case 14: return launch_step_nf<T, 14>(a, blocks, sh, st);
-    case 15: return launch_step_nf<T, 15>(a, blocks, sh, st);
-    case 16: return launch_step_nf<T, 16>(a, blocks, sh, st);
+    case 6: return launch_step_nf<T, 6, CFL>(a, blocks, sh, st);
+    case 7: return launch_step_nf<T, 7, CFL>(a, blocks, sh, st);
+    case 8: return launch_step_nf<T, 8, CFL>(a, blocks, sh, st);
+    case 9: return launch_step_nf<T, 9, CFL>(a, blocks, sh, st);
+    case 10: return launch_step_nf<T, 10, CFL>(a, blocks, sh, st);
+    case 11: return launch_step_nf<T, 11, CFL>(a, blocks, sh, st);
+    case 12: return launch_step_nf<T, 12, CFL>(a, blocks, sh, st);
+    case 13: return launch_step_nf<T, 13, CFL>(a, blocks, sh, st);
+    case 14: return launch_step_nf<T, 14, CFL>(a, blocks, sh, st);
+    case 15: return launch_step_nf<T, 15, CFL>(a, blocks, sh, st);
+    case 16: return launch_step_nf<T, 16, CFL>(a, blocks, sh, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1571,6 +1636,8 @@ inline hipError_t launch_step3d_t(const StepArgs& a, int blocks, const T* G, hip
 // One translation unit each.
 hipError_t launch_step_f64(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
 hipError_t launch_step_f32(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
+hipError_t launch_step_f64_cfl(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
+hipError_t launch_step_f32_cfl(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
 hipError_t launch_step3d(const StepArgs& a, int dtype, int blocks, const void* G, hipStream_t st);
 
 }  // namespace octohydro

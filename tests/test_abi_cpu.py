@@ -130,6 +130,8 @@ def test_step_rejects_aliasing_and_flags_on_the_host(hb):
     assert lib.hydro_step(None, None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
     assert lib.hydro_rk3_step(ctypes.byref(g), a, b, b, a, 0.4, a, None) == hb.HYDRO_E_ARG
     assert lib.hydro_graph_launch(None, None) == hb.HYDRO_E_ARG
+    assert lib.hydro_cfl_dt(ctypes.byref(g), a, -0.4, b, None) == hb.HYDRO_E_ARG
+    assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 16, None) == hb.HYDRO_E_ARG
     assert lib.hydro_check_status(ctypes.byref(g), None) == hb.HYDRO_E_ARG
 
 
@@ -145,9 +147,21 @@ def test_launch_options_roundtrip_and_validation(hb):
             hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_LEAF, 2)
             assert hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_LEAF) == 2
             hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_WAVES_PER_LEAF, l0)
-    # two wavefronts per leaf need passive species; 1 or 2 only
+    for epi in (0, 1):
+        e0 = hb.hydro_get_option(1, 11, hb.HYDRO_OPT_CFL_EPILOGUE)
+        hb.hydro_set_option(1, 11, hb.HYDRO_OPT_CFL_EPILOGUE, epi)
+        assert hb.hydro_get_option(1, 11, hb.HYDRO_OPT_CFL_EPILOGUE) == epi
+        hb.hydro_set_option(1, 11, hb.HYDRO_OPT_CFL_EPILOGUE, e0)
+    for remap in (0, 1, 2, 64, 4096):
+        r0 = hb.hydro_get_option(0, 11, hb.HYDRO_OPT_XCD_REMAP)
+        hb.hydro_set_option(0, 11, hb.HYDRO_OPT_XCD_REMAP, remap)
+        assert hb.hydro_get_option(0, 11, hb.HYDRO_OPT_XCD_REMAP) == remap
+        hb.hydro_set_option(0, 11, hb.HYDRO_OPT_XCD_REMAP, r0)
+    # two wavefronts per leaf need passive species; 1 or 2 only; remap 0, 1
+    # or a power of two up to 4096
     for bad in ((0, 6, 1, 3), (0, 5, 1, 1), (2, 6, 1, 1), (0, 6, 9, 1), (1, 17, 2, 1),
-                (0, 6, 2, 5), (0, 6, 3, 2), (1, 11, 3, 3), (0, 11, 3, 0)):
+                (0, 6, 2, 5), (0, 6, 2, -1), (0, 6, 2, 8192), (0, 6, 3, 2), (1, 11, 3, 3),
+                (0, 11, 3, 0), (0, 11, 4, 2)):
         with pytest.raises(hb.HydroError) as e:
             hb.hydro_set_option(*bad)
         assert e.value.code == hb.HYDRO_E_ARG
@@ -159,8 +173,13 @@ def test_recorded_tuning_is_well_formed(hb):
         pytest.skip("no tuning recorded yet")
     data = json.load(open(hb.TUNING_PATH))
     for e in data["entries"]:
-        assert e["waves_per_simd"] in (1, 2) and e["xcd_remap"] in (0, 1)
+        assert e["waves_per_simd"] in (1, 2) and e.get("waves_per_leaf", 1) in (1, 2)
+        r = e["xcd_remap"]
+        assert r in (0, 1) or (2 <= r <= 4096 and r & (r - 1) == 0)
         assert 6 <= e["n_fields"] <= 16 and e["dtype"] in (0, 1)
+        # every measured variant is recorded, and the choice is the fastest
+        assert len(e["all"]) >= 8
+        assert e["ms"] == min(v["ms"] for v in e["all"])
 
 
 def test_product_path_has_no_oracle_dependency():

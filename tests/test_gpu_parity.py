@@ -537,3 +537,123 @@ def test_dual_energy_branch_matches_oracle(env, name, make):
     print("  FP32-mixed per-field L1 after one RK3 step:", " ".join(f"{x:.2e}" for x in l1))
     assert hb.hydro_check_status(grid32) == hb.HYDRO_OK
     assert np.all(l1 < 1e-5), l1
+
+
+# -- chained time steps (CFL minimum taken by the last substep) ---------------
+
+CHAIN_CASES = [("uniform-base2-nf6", lambda: inputs.random_smooth(inputs.uniform_leaves(2), 2,
+                                                                  nf=6, seed=1), {}, 0, 1),
+               ("amr-base4-nf11", lambda: inputs.blobs(base=4, max_level=3), {}, 0, 1),
+               ("amr-base4-nf11-two-waves", lambda: inputs.blobs(base=4, max_level=3), {}, 0, 2),
+               ("amr-base2-nf11-reflux", lambda: inputs.blobs(base=2, max_level=2, threshold=0.5),
+                {"reflux": True}, 0, 1),
+               ("sod-base4-f32", lambda: inputs.sod(base=4), {}, 1, 1),
+               ("amr-base2-nf11-3d", lambda: inputs.blobs(base=2, max_level=2, threshold=0.5),
+                {"reconstruction": 1}, 0, 1)]
+
+
+@pytest.mark.parametrize("name,make,kw,dtype,leaf_waves", CHAIN_CASES,
+                         ids=[c[0] for c in CHAIN_CASES])
+def test_chained_time_steps_equal_the_plain_ones(env, name, make, kw, dtype, leaf_waves):
+    """Three RK3 steps with the time step taken from the minimum the last
+    substep left (hydro_grid.cfl_epilogue), eagerly and as a replayed graph,
+    against three plain RK3 steps (a CFL pass over each Un): the same time
+    steps and the same states, bit for bit; binary64 also against the oracle."""
+    torch, hb = env
+    w = make()
+    print(f"case {name}: {w.n_leaves} leaves nf={w.nf}", flush=True)
+    tdt = torch.float64 if dtype == 0 else torch.float32
+    plain = hb.Grid(w.leaf_coord, w.base, w.nf, dtype, **kw)
+    chain = hb.Grid(w.leaf_coord, w.base, w.nf, dtype, cfl_epilogue=True, **kw)
+    old = hb.hydro_get_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF)
+    hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, leaf_waves)
+    try:
+        U0 = torch.from_numpy(w.U).to("cuda").to(tdt).contiguous()
+        states = {}
+        for mode in ("plain", "chain", "graph"):
+            grid = plain if mode == "plain" else chain
+            U = U0.clone()
+            W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
+            dt = torch.zeros(2, dtype=torch.float64, device="cuda")
+            if mode != "plain":
+                hb.hydro_cfl_dt(grid, U, 0.0, dt[1:])
+            dts = []
+            if mode == "graph":
+                gA = hb.Rk3Graph(grid, U, W1, W2, Un, 0.4, dt)
+                gB = hb.Rk3Graph(grid, Un, W1, W2, U, 0.4, dt)
+                for i in range(3):
+                    (gA if i % 2 == 0 else gB).launch()
+                    dts.append(dt[0].item())
+                gA.close()
+                gB.close()
+                out = Un  # after steps A, B, A
+            else:
+                for _ in range(3):
+                    hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.4, dt)
+                    dts.append(dt[0].item())
+                    U, Un = Un, U
+                out = U
+            assert hb.hydro_check_status(grid) == hb.HYDRO_OK
+            states[mode] = (out.cpu().numpy().copy(), dts, dt[1].item())
+        ref_state, ref_dts, _ = states["plain"]
+        for mode in ("chain", "graph"):
+            got, dts, nxt = states[mode]
+            assert dts == ref_dts, (mode, dts, ref_dts)
+            assert np.array_equal(got, ref_state), mode
+        # the minimum left after the third step is that of the final state
+        T = oracle.Table(w.leaf_coord, w.base)
+        want = oracle.cfl_dt(T, ref_state.astype(np.float64), 1.0)
+        assert states["chain"][2] == want, (states["chain"][2], want)
+        if dtype == 0 and "reconstruction" not in kw:
+            Uo = w.U
+            for i in range(3):
+                Uo, dto, _ = oracle.rk3_step(T, Uo, 0.4, reflux=bool(kw.get("reflux")))
+                assert dto == ref_dts[i]
+            assert np.all(_rel(ref_state, Uo) <= TOL64)
+    finally:
+        hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, old)
+
+
+def test_step_flag_cfl_next_leaves_the_output_minimum(env):
+    torch, hb = env
+    for name, w, kw in (("amr-base4-nf11", inputs.blobs(base=4, max_level=3), {}),
+                        ("amr-base2-nf11-reflux", inputs.blobs(base=2, max_level=2,
+                                                               threshold=0.5), {"reflux": True})):
+        print(f"case {name}: {w.n_leaves} leaves", flush=True)
+        grid = hb.Grid(w.leaf_coord, w.base, w.nf, hb.HYDRO_F64, **kw)
+        T = oracle.Table(w.leaf_coord, w.base)
+        U = torch.from_numpy(w.U).to("cuda")
+        dt_o = oracle.cfl_dt(T, w.U, 0.4)
+        dt = torch.tensor([dt_o, -1.0], dtype=torch.float64, device="cuda")
+        out = grid.empty_state()
+        hb.hydro_step(grid, None, U, out, dt, 1.0, flags=hb.HYDRO_FLAG_CFL_NEXT)
+        got = out.cpu().numpy()
+        assert dt[0].item() == dt_o
+        assert dt[1].item() == oracle.cfl_dt(T, got, 1.0)
+
+
+@pytest.mark.parametrize("leaf_waves", [1, 2])
+def test_every_xcd_remap_gives_the_same_bits(env, leaf_waves):
+    """Leaves dealt to the XCDs in launch order, as contiguous ranges, or in
+    chunks (with a tail of leaves past the last whole round) all compute
+    every leaf exactly once: the same bits as the oracle."""
+    torch, hb = env
+    w = inputs.blobs(base=4, max_level=3)  # 4404 leaves: chunk rounds leave a tail
+    print(f"case amr-base4 remap sweep: {w.n_leaves} leaves", flush=True)
+    grid, T, U = _setup(env, w)
+    dt_o = oracle.cfl_dt(T, w.U, 0.4)
+    dt = torch.tensor([dt_o], dtype=torch.float64, device="cuda")
+    ref, _ = oracle.step(T, w.U, dt_o)
+    old = (hb.hydro_get_option(0, w.nf, hb.HYDRO_OPT_XCD_REMAP),
+           hb.hydro_get_option(0, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF))
+    hb.hydro_set_option(0, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, leaf_waves)
+    try:
+        for remap in (0, 1, 2, 64, 512, 4096):
+            hb.hydro_set_option(0, w.nf, hb.HYDRO_OPT_XCD_REMAP, remap)
+            out = grid.empty_state()
+            out.fill_(float("nan"))
+            hb.hydro_step(grid, None, U, out, dt, 1.0)
+            assert np.array_equal(out.cpu().numpy(), ref), remap
+    finally:
+        hb.hydro_set_option(0, w.nf, hb.HYDRO_OPT_XCD_REMAP, old[0])
+        hb.hydro_set_option(0, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, old[1])
