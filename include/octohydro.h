@@ -179,6 +179,17 @@ typedef struct hydro_grid {
    * reconstruction a pass over Unext does it).  The time steps are the same
    * bits as with 0. */
   int32_t cfl_epilogue;
+  /* Restricted copies made by the substeps themselves (Sec. VI: no separate
+   * buffers of ghost data): with a second caller-owned node buffer of
+   * node_state_dev's size and layout, and leaf_node_dev (int32 [n_leaves]:
+   * node * 8 + octant of each leaf that is a child of a refined node, else
+   * -1; from hydro_build_leaf_node), an RK3 step makes the node copies of Un
+   * in a pass and the first two substeps leave those of their outputs as
+   * they store them, so the other substeps need no pass.  Ignored with the
+   * flux correction or the 3D reconstruction.  Both NULL: a pass before
+   * every substep.  Same bits either way. */
+  void* node_state2_dev;
+  const int32_t* leaf_node_dev;
 } hydro_grid;
 
 /*
@@ -207,6 +218,15 @@ int hydro_build_reflux(int32_t n_leaves, const int32_t* leaf_coord, const int32_
 int hydro_build_table(int32_t n_leaves, int32_t base, const int32_t* leaf_coord,
                       int32_t* nbr, uint8_t* kind, int32_t* children,
                       int32_t max_nodes, int32_t* n_nodes_out);
+
+/*
+ * For each leaf, node * 8 + octant if it is child `octant` of a row of the
+ * children table (children[node][octant] == leaf), else -1; host arrays,
+ * children [n_nodes][8] in, leaf_node [n_leaves] out.  Returns HYDRO_E_TABLE
+ * if a leaf id is out of range or a leaf is listed twice.  Host only.
+ */
+int hydro_build_leaf_node(int32_t n_leaves, int32_t n_nodes, const int32_t* children,
+                          int32_t* leaf_node);
 
 /*
  * Ghost fill (Sec. VI: neighbours read directly, no message buffers): writes
@@ -338,6 +358,10 @@ const char* hydro_last_error(void);
  *                             minimum of its output (HYDRO_FLAG_CFL_NEXT,
  *                             chained RK3 steps) takes it: in the substep
  *                             kernel itself, or in a pass over the output
+ *   HYDRO_OPT_FUSED_RESTRICT  1 or 0: whether an RK3 step with
+ *                             node_state2_dev lets its substeps leave the
+ *                             node copies of their outputs (1) or makes
+ *                             them in a pass before each substep (0)
  * Every choice computes the same bits.  Options are process-wide and take effect at the next launch (a captured
  * graph keeps the kernel it was captured with).  Host only, thread-safe.
  */
@@ -345,6 +369,7 @@ const char* hydro_last_error(void);
 #define HYDRO_OPT_XCD_REMAP 2
 #define HYDRO_OPT_WAVES_PER_LEAF 3
 #define HYDRO_OPT_CFL_EPILOGUE 4
+#define HYDRO_OPT_FUSED_RESTRICT 5
 int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t value);
 int hydro_get_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t* value);
 

@@ -8,9 +8,10 @@ For each (dtype, n_fields) it times every combination of
     chunks of 64 or 512 consecutive leaves dealt to the XCDs in turn,
 on a workload of the benchmark's shape (the later-stage substep, which reads
 U0), through the C-ABI, and records the fastest in ``tuning.json`` next to
-this file with every measured variant; then, in the chosen shape, whether
-the last substep of a chained RK3 step takes the next CFL minimum in the
-kernel or in a pass over its output.  Every choice computes the same bits.
+this file with every measured variant; then, in the chosen shape and on
+whole chained RK3 steps, whether the last substep takes the next CFL minimum
+in its kernel or in a pass over its output, and whether the substeps leave
+the restricted node copies of their outputs or passes make them.  Every choice computes the same bits.
 ``binding.py`` applies the recorded choices when it is imported.
 
 Run on the GPU:  python -m paper_2210_06437_amd.autotune [--quick]
@@ -74,26 +75,47 @@ def tune_workload(torch, w, dtype, reps=5):
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_SIMD, best["waves_per_simd"])
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, best["waves_per_leaf"])
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_XCD_REMAP, best["xcd_remap"])
-    # the last substep of a chained RK3 step in the chosen shape: the CFL
-    # minimum of its output taken in the kernel, or in a pass after it
+    # in the chosen shape, the RK3 step's own choices, timed on whole
+    # chained RK3 steps: where the next CFL minimum is taken (the last
+    # substep's kernel, or a pass over its output) and where the node copies
+    # are made (left by the substeps, or a pass before each)
+    step_grid = hb.Grid(w.leaf_coord, w.base, w.nf, dtype, cfl_epilogue=True)
+    X = torch.from_numpy(w.U).to("cuda").to(tdt).contiguous()
+    Y, W1, W2 = step_grid.empty_state(), step_grid.empty_state(), step_grid.empty_state()
     dt2 = torch.zeros(2, dtype=torch.float64, device="cuda")
-    dt2[0] = dt[0]
-    cfl = []
+    hb.hydro_cfl_dt(step_grid, X, 0.0, dt2[1:])
+    step = []
     for epi in (1, 0):
-        hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_CFL_EPILOGUE, epi)
-        ms = _time_step(torch, grid, U, A, B, dt2, reps, hb.HYDRO_FLAG_CFL_NEXT)
-        cfl.append({"cfl_epilogue": epi, "ms": ms})
-        print(f"[autotune] dtype={dtype} nf={w.nf} last substep, CFL "
-              f"{'in the kernel' if epi else 'in a pass'}: {ms:.3f} ms",
-              file=sys.stderr, flush=True)
-    epi = min(cfl, key=lambda r: r["ms"])["cfl_epilogue"]
+        for fr in (1, 0):
+            hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_CFL_EPILOGUE, epi)
+            hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_FUSED_RESTRICT, fr)
+            best_ms = float("inf")
+            for i in range(reps + 1):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                hb.hydro_rk3_step(step_grid, X, W1, W2, Y, w.cfl, dt2)
+                e1.record()
+                torch.cuda.synchronize()
+                X, Y = Y, X
+                if i:
+                    best_ms = min(best_ms, e0.elapsed_time(e1))
+            step.append({"cfl_epilogue": epi, "fused_restrict": fr, "ms": best_ms})
+            print(f"[autotune] dtype={dtype} nf={w.nf} RK3 step, CFL "
+                  f"{'in the kernel' if epi else 'in a pass'}, node copies "
+                  f"{'by the substeps' if fr else 'in passes'}: {best_ms:.3f} ms",
+                  file=sys.stderr, flush=True)
+    pick = min(step, key=lambda r: r["ms"])
+    epi, fr = pick["cfl_epilogue"], pick["fused_restrict"]
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_CFL_EPILOGUE, epi)
+    hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_FUSED_RESTRICT, fr)
+    del X, Y, W1, W2, step_grid
     del U, A, B
     torch.cuda.empty_cache()
     return {"dtype": dtype, "n_fields": w.nf, "waves_per_simd": best["waves_per_simd"],
             "waves_per_leaf": best["waves_per_leaf"], "xcd_remap": best["xcd_remap"],
-            "cfl_epilogue": epi, "ms": best["ms"], "workload": w.name, "leaves": w.n_leaves,
-            "all": results, "last_substep": cfl}
+            "cfl_epilogue": epi, "fused_restrict": fr, "ms": best["ms"], "workload": w.name,
+            "leaves": w.n_leaves, "all": results, "rk3_step": step}
 
 
 def main():
@@ -116,7 +138,7 @@ def main():
         json.dump(out, f, indent=1)
     print(json.dumps({"wrote": args.out, "choices": [
         {k: e[k] for k in ("dtype", "n_fields", "waves_per_simd", "waves_per_leaf", "xcd_remap",
-                           "cfl_epilogue", "ms")}
+                           "cfl_epilogue", "fused_restrict", "ms")}
         for e in entries]}))
 
 

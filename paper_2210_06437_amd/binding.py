@@ -39,10 +39,11 @@ EXPORTS = [
     "hydro_cfl_dt", "hydro_totals", "hydro_rk3_step", "hydro_rk3_graph_create",
     "hydro_graph_launch", "hydro_graph_destroy", "hydro_check_status", "hydro_last_error",
     "hydro_version", "hydro_set_option", "hydro_get_option", "hydro_build_reflux",
-    "hydro_totals_noalloc",
+    "hydro_totals_noalloc", "hydro_build_leaf_node",
 ]
 HYDRO_OPT_WAVES_PER_SIMD, HYDRO_OPT_XCD_REMAP, HYDRO_OPT_WAVES_PER_LEAF = 1, 2, 3
 HYDRO_OPT_CFL_EPILOGUE = 4
+HYDRO_OPT_FUSED_RESTRICT = 5
 
 
 class HydroError(RuntimeError):
@@ -76,6 +77,8 @@ class hydro_grid(ctypes.Structure):
         ("node_state_dev", ctypes.c_void_p),
         ("ghost_tile_dev", ctypes.c_void_p),
         ("cfl_epilogue", ctypes.c_int32),
+        ("node_state2_dev", ctypes.c_void_p),
+        ("leaf_node_dev", ctypes.c_void_p),
     ]
 
 
@@ -106,6 +109,7 @@ def _load():
         "hydro_build_reflux": ([i32, vp, vp, vp, vp, vp, vp, i32, vp, ctypes.POINTER(i32)],
                                ctypes.c_int),
         "hydro_get_option": ([i32, i32, i32, ctypes.POINTER(i32)], ctypes.c_int),
+        "hydro_build_leaf_node": ([i32, i32, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -135,6 +139,8 @@ def apply_tuning(path: str = TUNING_PATH) -> int:
                               int(e.get("waves_per_leaf", 1)))
         _lib.hydro_set_option(int(e["dtype"]), int(e["n_fields"]), 4,
                               int(e.get("cfl_epilogue", 1)))
+        _lib.hydro_set_option(int(e["dtype"]), int(e["n_fields"]), 5,
+                              int(e.get("fused_restrict", 1)))
         n += 1
     return n
 
@@ -192,6 +198,15 @@ def hydro_build_table(leaf_coord: np.ndarray, base: int):
     return nbr, kind, np.ascontiguousarray(kids[: nn.value])
 
 
+def hydro_build_leaf_node(n_leaves: int, children: np.ndarray):
+    """node * 8 + octant of every child leaf of the children table, else -1."""
+    kids = np.ascontiguousarray(children, dtype=np.int32).reshape(-1, 8)
+    out = np.zeros(int(n_leaves), np.int32)
+    _check(_lib.hydro_build_leaf_node(int(n_leaves), len(kids), kids.ctypes.data,
+                                      out.ctypes.data))
+    return out
+
+
 def hydro_build_reflux(leaf_coord: np.ndarray, nbr: np.ndarray, kind: np.ndarray):
     """Host flux-register tables: (face_slot [n][6], fine_slot [n][6],
     slot_leaf [n_slots], orient_begin [7])."""
@@ -216,11 +231,12 @@ class Grid:
     hydro_grid struct that points at it.  reflux=True also builds the
     flux-register tables and scratch, which turns on the coarse-fine flux
     correction.  cfl_epilogue=True chains the RK3 steps' time steps (dt of
-    2 doubles; see hydro_grid.cfl_epilogue)."""
+    2 doubles; see hydro_grid.cfl_epilogue).  fused_restrict=False keeps a
+    restriction pass before every RK3 substep (see hydro_grid.node_state2_dev)."""
 
     def __init__(self, leaf_coord, base, n_fields, dtype=HYDRO_F64, gamma=5.0 / 3.0,
                  eta1=1e-3, device="cuda", reflux=False, omega=0.0,
-                 reconstruction=HYDRO_RECON_AXIS, cfl_epilogue=False):
+                 reconstruction=HYDRO_RECON_AXIS, cfl_epilogue=False, fused_restrict=True):
         coord = np.ascontiguousarray(leaf_coord, dtype=np.int32)
         nbr, kind, kids = hydro_build_table(coord, base)
         self.host_nbr, self.host_kind, self.host_children = nbr, kind, kids
@@ -253,6 +269,14 @@ class Grid:
             self.node_state = torch.empty((self.n_fields, len(kids), 8, 8, 8),
                                           dtype=self.torch_dtype, device=dev)
             self.c.node_state_dev = self.node_state.data_ptr()
+            if fused_restrict:
+                # a second node buffer: RK3 substeps leave the node copies of
+                # their outputs for the next substep
+                self.node_state2 = torch.empty_like(self.node_state)
+                self.leaf_node = torch.from_numpy(
+                    hydro_build_leaf_node(self.n_leaves, kids)).to(dev)
+                self.c.node_state2_dev = self.node_state2.data_ptr()
+                self.c.leaf_node_dev = self.leaf_node.data_ptr()
         self.reflux = bool(reflux)
         if self.reflux:
             fs, fi, sl, ob = hydro_build_reflux(coord, nbr, kind)

@@ -5,7 +5,7 @@
 namespace octohydro {
 
 hipError_t launch_step_f32_cfl(const StepArgs& a, int blocks, StepShape sh, hipStream_t st) {
-  return launch_step_t<float, true>(a, blocks, sh, st);
+  return launch_step_t<float, STEP_CFL>(a, blocks, sh, st);
 }
 
 }  // namespace octohydro

@@ -5,7 +5,7 @@
 namespace octohydro {
 
 hipError_t launch_step_f64(const StepArgs& a, int blocks, StepShape sh, hipStream_t st) {
-  return launch_step_t<double, false>(a, blocks, sh, st);
+  return launch_step_t<double, STEP_PLAIN>(a, blocks, sh, st);
 }
 
 }  // namespace octohydro

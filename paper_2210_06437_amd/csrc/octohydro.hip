@@ -297,6 +297,7 @@ static GridArgs grid_args(const hydro_grid* gr) {
   g.reg = reflux ? gr->flux_reg_dev : nullptr;
   g.omega = gr->omega;
   g.rstate = gr->n_nodes > 0 ? gr->node_state_dev : nullptr;
+  g.leaf_node = gr->leaf_node_dev;
   return g;
 }
 
@@ -364,6 +365,7 @@ struct Options {
   int xcd_remap = 1;
   int waves_per_leaf = 1;
   int cfl_epilogue = 1;
+  int fused_restrict = 1;
 };
 static Options g_opts[2][17];
 static std::mutex g_opts_mu;
@@ -386,9 +388,13 @@ static hipError_t launch_step(StepArgs a, int dtype, int blocks, hipStream_t st)
   const Options o = get_options(dtype, a.g.nf);
   if (a.remap) a.remap = o.xcd_remap;
   const StepShape sh{o.waves_per_simd, o.waves_per_leaf};
+  if (a.dt_next && a.node_out) return hipErrorInvalidValue;  // no kernel does both
   if (a.dt_next)
     return dtype == HYDRO_F64 ? launch_step_f64_cfl(a, blocks, sh, st)
                               : launch_step_f32_cfl(a, blocks, sh, st);
+  if (a.node_out)
+    return dtype == HYDRO_F64 ? launch_step_f64_restrict(a, blocks, sh, st)
+                              : launch_step_f32_restrict(a, blocks, sh, st);
   return dtype == HYDRO_F64 ? launch_step_f64(a, blocks, sh, st)
                             : launch_step_f32(a, blocks, sh, st);
 }
@@ -430,6 +436,10 @@ static int step_common(const hydro_grid* gr, const void* U0, const void* Uk, voi
     if (node_bytes > OFF_NONE)
       return fail(HYDRO_E_ARG, "%s: node_state of %llu bytes exceeds 4 GiB - 4 KiB", fn,
                   (unsigned long long)node_bytes);
+    if (gr->node_state2_dev && (gr->node_state2_dev == gr->node_state_dev ||
+                                gr->node_state2_dev == Uk || gr->node_state2_dev == Uout ||
+                                (U0 && gr->node_state2_dev == U0)))
+      return fail(HYDRO_E_ARG, "%s: node_state2_dev aliases another buffer", fn);
   }
   a.g = grid_args(gr);
   a.U0 = U0;
@@ -440,6 +450,7 @@ static int step_common(const hydro_grid* gr, const void* U0, const void* Uk, voi
   a.leaf_base = 0;
   a.remap = 1;
   a.dt_next = nullptr;
+  a.node_out = nullptr;
   return HYDRO_OK;
 }
 
@@ -505,19 +516,35 @@ static int rk3_launch(const hydro_grid* gr, const void* Un, void* W1, void* W2, 
     rc = cfl_launch(gr, Un, cfl, dt, st);
     if (rc) return rc;
   }
+  // restricted node copies: made by a pass before each substep, or, with a
+  // second node buffer, only before the first, the first two substeps then
+  // leaving those of their outputs for the next (not with the flux
+  // correction, which changes cells after the kernel)
+  const bool fused = gr->node_state2_dev && gr->leaf_node_dev && gr->n_nodes > 0 &&
+                     gr->reconstruction == HYDRO_RECON_AXIS && !a.g.reg &&
+                     get_options(gr->dtype, gr->n_fields).fused_restrict != 0;
+  if (fused) a.node_out = gr->node_state2_dev;
   if ((rc = substep_kernels(gr, a, gr->n_leaves, true, st))) return rc;
   if ((rc = reflux_launch(gr, a, st))) return rc;
   a.U0 = Un;
   a.Uk = W1;
   a.Uout = W2;
   a.beta = 0.25;
-  if ((rc = substep_kernels(gr, a, gr->n_leaves, true, st))) return rc;
+  if (fused) {
+    a.g.rstate = gr->node_state2_dev;
+    a.node_out = gr->node_state_dev;
+  }
+  if ((rc = substep_kernels(gr, a, gr->n_leaves, !fused, st))) return rc;
   if ((rc = reflux_launch(gr, a, st))) return rc;
   a.Uk = W2;
   a.Uout = Unext;
   a.beta = 2.0 / 3.0;
+  if (fused) {
+    a.g.rstate = gr->node_state_dev;
+    a.node_out = nullptr;
+  }
   if (chained && cfl_in_kernel(gr, a)) a.dt_next = dt + 1;
-  if ((rc = substep_kernels(gr, a, gr->n_leaves, true, st))) return rc;
+  if ((rc = substep_kernels(gr, a, gr->n_leaves, !fused, st))) return rc;
   if ((rc = reflux_launch(gr, a, st))) return rc;
   if (chained && !a.dt_next) return cfl_launch(gr, Unext, 0.0, dt + 1, st);
   return HYDRO_OK;
@@ -622,6 +649,11 @@ int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t va
                     "hydro_set_option: remap is 0, 1 or a power of two in [2, 4096]");
       o.xcd_remap = value;
       return HYDRO_OK;
+    case HYDRO_OPT_FUSED_RESTRICT:
+      if (value != 0 && value != 1)
+        return fail(HYDRO_E_ARG, "hydro_set_option: fused restriction is 0 or 1");
+      o.fused_restrict = value;
+      return HYDRO_OK;
     case HYDRO_OPT_CFL_EPILOGUE:
       if (value != 0 && value != 1)
         return fail(HYDRO_E_ARG, "hydro_set_option: CFL epilogue is 0 or 1");
@@ -648,6 +680,7 @@ int hydro_get_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t* v
   else if (option == HYDRO_OPT_XCD_REMAP) *value = o.xcd_remap;
   else if (option == HYDRO_OPT_WAVES_PER_LEAF) *value = o.waves_per_leaf;
   else if (option == HYDRO_OPT_CFL_EPILOGUE) *value = o.cfl_epilogue;
+  else if (option == HYDRO_OPT_FUSED_RESTRICT) *value = o.fused_restrict;
   else return fail(HYDRO_E_ARG, "hydro_get_option: unknown option %d", option);
   return HYDRO_OK;
 }

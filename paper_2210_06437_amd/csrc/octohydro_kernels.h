@@ -47,6 +47,8 @@ struct GridArgs {
   double* reg;
   double omega;  // rotating-frame angular velocity (0: no sources)
   void* rstate;  // restricted copies of the refined nodes [nf][n_nodes][512]
+  // node * 8 + octant of each leaf that is a child of a refined node, or -1
+  const int32_t* leaf_node;
 };
 
 // Values per register slot and field: 64 coarse face fluxes, then the 16x16
@@ -303,7 +305,67 @@ struct StepArgs {
   // takes part in the global time-step size) into *dt_next (a binary64
   // whose bit pattern is reduced with an unsigned 64-bit atomic min)
   double* dt_next;
+  // Restricted copies of the output: when set, every leaf that is a child of
+  // a refined node also writes the coarse (8-cell mean) cells its output
+  // covers into this [nf][n_nodes][512] array, in the order of the ghost
+  // fill's restriction, for the next substep's refined-side ghosts.
+  void* node_out;
 };
+
+// Kernel variants of the fused substep (see k_step).
+constexpr int STEP_PLAIN = 0;
+constexpr int STEP_RESTRICT = 1;
+constexpr int STEP_CFL = 2;
+
+// Coarse cell of node copy that leaf cell (x, y, z) lies in, for a leaf in
+// octant `oct` (x + 2 y + 4 z of the child position) of its node.
+__device__ __forceinline__ int coarse_cell(int oct, int x, int y, int z) {
+  return (4 * (oct >> 2) + (z >> 1)) * 64 + (4 * ((oct >> 1) & 1) + (y >> 1)) * 8 +
+         (4 * (oct & 1) + (x >> 1));
+}
+
+// Restriction of stored output values as a by-product of the Z phase.  Lane
+// (x, y) finishes cells (x, y, z) for consecutive z; the 2x2 transverse sum
+// of a plane, ((v(x) + v(x^1)) + (v(y^1) + v(x^1, y^1))), is the same in all
+// four lanes of the group (both additions commute).  At even z it is parked
+// in the cell's accumulator slot (read already); at odd z the parked sum of
+// z - 1 and this plane's sum give the coarse value
+// 0.125 * ((sum at z - 1) + (sum at z)), which the lane at even (x, y)
+// stores.  That is 0.125 * (((v000 + v100) + (v010 + v110)) + ((v001 + v101)
+// + (v011 + v111))), the ghost fill's order, in the element type.
+// Value of lane ^ 1 (DPP quad permutation [1,0,3,2]) and of lane ^ 8 (DPP
+// rotation by 8 within a row of 16 lanes): register moves between lanes,
+// no LDS traffic.
+constexpr int DPP_XOR1 = 0xB1;
+constexpr int DPP_XOR8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <typename T>
+__device__ __forceinline__ void restrict_out(const StepArgs& s, double* __restrict__ slot,
+                                             int node, int f, int x, int y, int z, T o) {
+  const T t = o + dpp_move<DPP_XOR1>(o);
+  const T q = t + dpp_move<DPP_XOR8>(t);
+  if ((z & 1) == 0) {
+    *slot = (double)q;
+  } else {
+    const T r = T(0.125) * ((T)slot[-ACC_PLANE] + q);
+    if (((x | y) & 1) == 0)
+      static_cast<T*>(s.node_out)[((size_t)f * s.g.n_nodes + (node >> 3)) * CELLS +
+                                  coarse_cell(node & 7, x, y, z)] = r;
+  }
+}
 
 // Per-cell CFL quantity dx / (max(|v_x|, |v_y|, |v_z|) + c) of a stored
 // state (rho, s, E, tau as stored, in binary64), evaluated operation by
@@ -731,11 +793,11 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
 // Phase Z of half h: lane (x, y) streams its z-pencil over stream positions
 // [4h, 4h+10), which yields the z-faces of cells z in [4h, 4h+4), adds dHz
 // to the accumulator and finishes those cells.
-template <typename T, int NF, bool CFL>
+template <typename T, int NF, int MODE>
 __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
-                                        const FaceNbr& fn, const double* __restrict__ acc, int h,
+                                        const FaceNbr& fn, double* __restrict__ acc, int h,
                                         int lane, double dt, double inv_dx, bool& bad,
-                                        double& cflmin) {
+                                        double& cflmin, int lnode) {
   const GridArgs& g = s.g;
   const size_t fs = (size_t)g.n_leaves * CELLS;
   const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
@@ -801,8 +863,11 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
                                    rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0,
                                    dt, inv_dx);
         if (f < NF_CORE) cv[f] = o;
+        if constexpr (MODE == STEP_RESTRICT) {
+          if (lnode >= 0) restrict_out<T>(s, &acc[f * ACC_HALF + ai], lnode, f, x, y, i, o);
+        }
       }
-      if constexpr (CFL) cflmin = fmin(cflmin, cfl_quantity<T>(g, cv, 1.0 / inv_dx));
+      if constexpr (MODE == STEP_CFL) cflmin = fmin(cflmin, cfl_quantity<T>(g, cv, 1.0 / inv_dx));
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) Hprev[f] = (double)H[f];
@@ -810,9 +875,11 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
 }
 
 // W = register budget: W waves per SIMD (1: up to 512 VGPRs, 2: up to 256).
-// CFL: the instantiation with the CFL epilogue (s.dt_next set), a separate
-// kernel so that the others keep its registers.
-template <typename T, int NF, int W, bool CFL>
+// MODE: STEP_PLAIN, STEP_RESTRICT (s.node_out set: the node copies of the
+// output are left as well) or STEP_CFL (s.dt_next set: the CFL minimum of
+// the output is taken as well); separate kernels, so that each keeps only
+// the registers its own work needs.
+template <typename T, int NF, int W, int MODE>
 __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
   __shared__ __align__(16) double acc[NF * ACC_HALF];
   const GridArgs& g = s.g;
@@ -864,14 +931,15 @@ __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
 
   bool bad = false;
   double cflmin = INFINITY;
+  const int lnode = MODE == STEP_RESTRICT ? g.leaf_node[leaf] : -1;
 #pragma unroll 1
   for (int h = 0; h < 2; ++h) {
     phase_xy<T, NF>(s, ph, li, fxy, acc, h, lane, bad);
     wave_lds_sync();
-    phase_z<T, NF, CFL>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad, cflmin);
+    phase_z<T, NF, MODE>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad, cflmin, lnode);
     wave_lds_sync();
   }
-  if constexpr (CFL) atomic_min_positive(s.dt_next, cflmin, lane);
+  if constexpr (MODE == STEP_CFL) atomic_min_positive(s.dt_next, cflmin, lane);
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
 }
 
@@ -1048,13 +1116,13 @@ __device__ __forceinline__ void phase_xy_group(const StepArgs& s, const Phys<T>&
 
 // Phase Z of half h for one field group (see phase_z); the core group adds
 // the rotating-frame sources.
-template <typename T, int NF, int F0, int NG, bool CFL>
+template <typename T, int NF, int F0, int NG, int MODE>
 __device__ __forceinline__ void phase_z_group(const StepArgs& s, const Phys<T>& ph,
                                               const LeafInfo& li, const FaceNbr& fn,
-                                              const double* __restrict__ acc,
+                                              double* __restrict__ acc,
                                               SpeedSlot<T>* __restrict__ spd, int& sn, int h,
                                               int lane, double dt, double inv_dx, bool& bad,
-                                              double& cflmin) {
+                                              double& cflmin, int lnode) {
   const GridArgs& g = s.g;
   const size_t fs = (size_t)g.n_leaves * CELLS;
   const uint32_t fs_b = (uint32_t)(fs * sizeof(T));
@@ -1120,8 +1188,12 @@ __device__ __forceinline__ void phase_z_group(const StepArgs& s, const Phys<T>& 
                                    rot && fg >= 1 && fg <= 4,
                                    fg >= 1 && fg <= 4 ? src[fg - 1] : 0.0, dt, inv_dx);
         if (F0 == 0 && f < NF_CORE) cv[f] = o;
+        if constexpr (MODE == STEP_RESTRICT) {
+          if (lnode >= 0) restrict_out<T>(s, &acc[fg * ACC_HALF + ai], lnode, fg, x, y, i, o);
+        }
       }
-      if constexpr (CFL && F0 == 0) cflmin = fmin(cflmin, cfl_quantity<T>(g, cv, 1.0 / inv_dx));
+      if constexpr (MODE == STEP_CFL && F0 == 0)
+        cflmin = fmin(cflmin, cfl_quantity<T>(g, cv, 1.0 / inv_dx));
     }
 #pragma unroll
     for (int f = 0; f < NG; ++f) Hprev[f] = (double)H[f];
@@ -1129,8 +1201,8 @@ __device__ __forceinline__ void phase_z_group(const StepArgs& s, const Phys<T>& 
 }
 
 // W = waves per SIMD the register budget allows (1: up to 512 VGPRs, 2: 256);
-// CFL as for k_step.
-template <typename T, int NF, int W, bool CFL>
+// MODE as for k_step.
+template <typename T, int NF, int W, int MODE>
 __global__ void __launch_bounds__(128, W) k_step2(StepArgs s) {
   static_assert(NF > NF_CORE, "the second wavefront needs passive species");
   __shared__ __align__(16) double acc[NF * ACC_HALF];
@@ -1186,6 +1258,7 @@ __global__ void __launch_bounds__(128, W) k_step2(StepArgs s) {
 
   bool bad = false;
   double cflmin = INFINITY;
+  const int lnode = MODE == STEP_RESTRICT ? g.leaf_node[leaf] : -1;
   int sn = 0;  // stream steps taken: selects the hand-off slot
   constexpr int NS = NF - NF_CORE;
 #pragma unroll 1
@@ -1196,14 +1269,14 @@ __global__ void __launch_bounds__(128, W) k_step2(StepArgs s) {
       phase_xy_group<T, NF, NF_CORE, NS>(s, ph, li, fxy, acc, spd, sn, h, lane, bad);
     wave_lds_sync();
     if (wave == 0)
-      phase_z_group<T, NF, 0, NF_CORE, CFL>(s, ph, li, fz, acc, spd, sn, h, lane, dt, inv_dx,
-                                            bad, cflmin);
+      phase_z_group<T, NF, 0, NF_CORE, MODE>(s, ph, li, fz, acc, spd, sn, h, lane, dt, inv_dx,
+                                            bad, cflmin, lnode);
     else
-      phase_z_group<T, NF, NF_CORE, NS, CFL>(s, ph, li, fz, acc, spd, sn, h, lane, dt, inv_dx,
-                                             bad, cflmin);
+      phase_z_group<T, NF, NF_CORE, NS, MODE>(s, ph, li, fz, acc, spd, sn, h, lane, dt, inv_dx,
+                                             bad, cflmin, lnode);
     wave_lds_sync();
   }
-  if constexpr (CFL) {
+  if constexpr (MODE == STEP_CFL) {
     if (wave == 0) atomic_min_positive(s.dt_next, cflmin, lane);
   }
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
@@ -1562,40 +1635,39 @@ struct StepShape {
   int waves_per_leaf;
 };
 
-template <typename T, int NF, bool CFL>
+template <typename T, int NF, int MODE>
 inline hipError_t launch_step_nf(const StepArgs& a, int blocks, StepShape sh, hipStream_t st) {
   if constexpr (NF > NF_CORE) {
     if (sh.waves_per_leaf == 2) {
       if (sh.waves_per_simd == 2)
-        hipLaunchKernelGGL((k_step2<T, NF, 2, CFL>), dim3(blocks), dim3(128), 0, st, a);
+        hipLaunchKernelGGL((k_step2<T, NF, 2, MODE>), dim3(blocks), dim3(128), 0, st, a);
       else
-        hipLaunchKernelGGL((k_step2<T, NF, 1, CFL>), dim3(blocks), dim3(128), 0, st, a);
+        hipLaunchKernelGGL((k_step2<T, NF, 1, MODE>), dim3(blocks), dim3(128), 0, st, a);
       return hipGetLastError();
     }
   }
   if (sh.waves_per_simd == 2)
-    hipLaunchKernelGGL((k_step<T, NF, 2, CFL>), dim3(blocks), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_step<T, NF, 2, MODE>), dim3(blocks), dim3(64), 0, st, a);
   else
-    hipLaunchKernelGGL((k_step<T, NF, 1, CFL>), dim3(blocks), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_step<T, NF, 1, MODE>), dim3(blocks), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
-// Launch of the fused substep for any field count; CFL selects the
-// instantiations with the CFL epilogue (a.dt_next set).
-template <typename T, bool CFL>
+// Launch of the fused substep for any field count in one MODE.
+template <typename T, int MODE>
 inline hipError_t launch_step_t(const StepArgs& a, int blocks, StepShape sh, hipStream_t st) {
   switch (a.g.nf) {
-    case 6: return launch_step_nf<T, 6, CFL>(a, blocks, sh, st);
-    case 7: return launch_step_nf<T, 7, CFL>(a, blocks, sh, st);
-    case 8: return launch_step_nf<T, 8, CFL>(a, blocks, sh, st);
-    case 9: return launch_step_nf<T, 9, CFL>(a, blocks, sh, st);
-    case 10: return launch_step_nf<T, 10, CFL>(a, blocks, sh, st);
-    case 11: return launch_step_nf<T, 11, CFL>(a, blocks, sh, st);
-    case 12: return launch_step_nf<T, 12, CFL>(a, blocks, sh, st);
-    case 13: return launch_step_nf<T, 13, CFL>(a, blocks, sh, st);
-    case 14: return launch_step_nf<T, 14, CFL>(a, blocks, sh, st);
-    case 15: return launch_step_nf<T, 15, CFL>(a, blocks, sh, st);
-    case 16: return launch_step_nf<T, 16, CFL>(a, blocks, sh, st);
+    case 6: return launch_step_nf<T, 6, MODE>(a, blocks, sh, st);
+    case 7: return launch_step_nf<T, 7, MODE>(a, blocks, sh, st);
+    case 8: return launch_step_nf<T, 8, MODE>(a, blocks, sh, st);
+    case 9: return launch_step_nf<T, 9, MODE>(a, blocks, sh, st);
+    case 10: return launch_step_nf<T, 10, MODE>(a, blocks, sh, st);
+    case 11: return launch_step_nf<T, 11, MODE>(a, blocks, sh, st);
+    case 12: return launch_step_nf<T, 12, MODE>(a, blocks, sh, st);
+    case 13: return launch_step_nf<T, 13, MODE>(a, blocks, sh, st);
+    case 14: return launch_step_nf<T, 14, MODE>(a, blocks, sh, st);
+    case 15: return launch_step_nf<T, 15, MODE>(a, blocks, sh, st);
+    case 16: return launch_step_nf<T, 16, MODE>(a, blocks, sh, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1638,6 +1710,8 @@ hipError_t launch_step_f64(const StepArgs& a, int blocks, StepShape sh, hipStrea
 hipError_t launch_step_f32(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
 hipError_t launch_step_f64_cfl(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
 hipError_t launch_step_f32_cfl(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
+hipError_t launch_step_f64_restrict(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
+hipError_t launch_step_f32_restrict(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
 hipError_t launch_step3d(const StepArgs& a, int dtype, int blocks, const void* G, hipStream_t st);
 
 }  // namespace octohydro

@@ -161,3 +161,23 @@ extern "C" int hydro_build_reflux(int32_t n_leaves, const int32_t* leaf_coord,
   *n_slots_out = n_slots;
   return HYDRO_OK;
 }
+
+// Inverse of the children table: the node and octant of every child leaf.
+extern "C" int hydro_build_leaf_node(int32_t n_leaves, int32_t n_nodes, const int32_t* children,
+                                     int32_t* leaf_node) {
+  octohydro::clear_error();
+  if (n_leaves <= 0 || n_nodes < 0 || !leaf_node || (n_nodes > 0 && !children))
+    return octohydro::fail(HYDRO_E_ARG, "hydro_build_leaf_node: bad arguments");
+  for (int32_t i = 0; i < n_leaves; ++i) leaf_node[i] = -1;
+  for (int32_t n = 0; n < n_nodes; ++n)
+    for (int o = 0; o < 8; ++o) {
+      const int32_t c = children[8 * n + o];
+      if (c < 0) continue;
+      if (c >= n_leaves)
+        return octohydro::fail(HYDRO_E_TABLE, "hydro_build_leaf_node: child %d out of range", c);
+      if (leaf_node[c] >= 0)
+        return octohydro::fail(HYDRO_E_TABLE, "hydro_build_leaf_node: leaf %d listed twice", c);
+      leaf_node[c] = 8 * n + o;
+    }
+  return HYDRO_OK;
+}

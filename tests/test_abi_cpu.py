@@ -161,7 +161,7 @@ def test_launch_options_roundtrip_and_validation(hb):
     # or a power of two up to 4096
     for bad in ((0, 6, 1, 3), (0, 5, 1, 1), (2, 6, 1, 1), (0, 6, 9, 1), (1, 17, 2, 1),
                 (0, 6, 2, 5), (0, 6, 2, -1), (0, 6, 2, 8192), (0, 6, 3, 2), (1, 11, 3, 3),
-                (0, 11, 3, 0), (0, 11, 4, 2)):
+                (0, 11, 3, 0), (0, 11, 4, 2), (0, 11, 5, 3)):
         with pytest.raises(hb.HydroError) as e:
             hb.hydro_set_option(*bad)
         assert e.value.code == hb.HYDRO_E_ARG
@@ -253,3 +253,27 @@ def test_reconstruction_mode_is_checked_on_the_host(hb):
     g = _raw_grid(hb, reconstruction=hb.HYDRO_RECON_3D, ghost_tile_dev=64)
     assert lib.hydro_step(ctypes.byref(g), None, a, b, a, 1.0, 0, None) == hb.HYDRO_E_ARG
     assert "alias" in hb.hydro_last_error()
+
+
+def test_leaf_node_table_inverts_the_children_table(hb):
+    for coord, base in _trees():
+        nbr, kind, kids = hb.hydro_build_table(coord, base)
+        ln = hb.hydro_build_leaf_node(len(coord), kids)
+        want = np.full(len(coord), -1, np.int32)
+        for n, row in enumerate(kids):
+            for o, c in enumerate(row):
+                if c >= 0:
+                    want[c] = 8 * n + o
+        assert np.array_equal(ln, want)
+        if len(kids):
+            # a child of a node sits in the octant its coordinates give
+            for i in np.nonzero(ln >= 0)[0]:
+                o = ln[i] & 7
+                L, x, y, z = coord[i]
+                assert o == (x & 1) + 2 * (y & 1) + 4 * (z & 1)
+    bad = np.array([[0, 1, 2, 3, 4, 5, 6, 0]], np.int32)  # leaf 0 listed twice
+    with pytest.raises(hb.HydroError) as e:
+        hb.hydro_build_leaf_node(8, bad)
+    assert e.value.code == hb.HYDRO_E_TABLE
+    with pytest.raises(hb.HydroError):
+        hb.hydro_build_leaf_node(4, np.array([[0, 1, 2, 9, -1, -1, -1, -1]], np.int32))

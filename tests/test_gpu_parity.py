@@ -657,3 +657,44 @@ def test_every_xcd_remap_gives_the_same_bits(env, leaf_waves):
     finally:
         hb.hydro_set_option(0, w.nf, hb.HYDRO_OPT_XCD_REMAP, old[0])
         hb.hydro_set_option(0, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, old[1])
+
+
+@pytest.mark.parametrize("dtype,leaf_waves", [(0, 1), (0, 2), (1, 1), (1, 2)])
+def test_node_copies_left_by_the_substeps_equal_the_restriction_pass(env, dtype, leaf_waves):
+    """RK3 steps whose first two substeps leave the restricted node copies of
+    their outputs (the default) against RK3 steps with a restriction pass
+    before every substep: the same bits, on an uneven tree where refined
+    nodes border coarse leaves in every direction; binary64 also against the
+    oracle."""
+    torch, hb = env
+    w = inputs.blobs(base=4, max_level=3)
+    print(f"case amr-base4 fused restriction dtype={dtype} waves/leaf={leaf_waves}: "
+          f"{w.n_leaves} leaves", flush=True)
+    tdt = torch.float64 if dtype == 0 else torch.float32
+    fused = hb.Grid(w.leaf_coord, w.base, w.nf, dtype)
+    plain = hb.Grid(w.leaf_coord, w.base, w.nf, dtype, fused_restrict=False)
+    assert fused.c.node_state2_dev and not plain.c.node_state2_dev
+    old = hb.hydro_get_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF)
+    old_fr = hb.hydro_get_option(dtype, w.nf, hb.HYDRO_OPT_FUSED_RESTRICT)
+    hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, leaf_waves)
+    hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_FUSED_RESTRICT, 1)
+    try:
+        outs = []
+        for grid in (fused, plain):
+            U = torch.from_numpy(w.U).to("cuda").to(tdt).contiguous()
+            W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
+            dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+            for _ in range(2):
+                hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.4, dt)
+                U, Un = Un, U
+            outs.append(U.cpu().numpy())
+        assert np.array_equal(outs[0], outs[1])
+        if dtype == 0:
+            T = oracle.Table(w.leaf_coord, w.base)
+            Uo = w.U
+            for _ in range(2):
+                Uo, _, _ = oracle.rk3_step(T, Uo, 0.4)
+            assert np.all(_rel(outs[0], Uo) <= TOL64)
+    finally:
+        hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, old)
+        hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_FUSED_RESTRICT, old_fr)
