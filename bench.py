@@ -336,14 +336,18 @@ TRAFFIC_PATH = os.path.join(ROOT, "profiles", "k_step_turbulence65k_f64_traffic.
 KERNEL_DIR = os.path.join(ROOT, "paper_2210_06437_amd", "csrc")
 
 
+# The sources the measured substep kernel is built from: its device code, its
+# plain-variant translation units, the public header and the build flags.
+STEP_SOURCES = ("octohydro_kernels.h", "k_step_f64.hip", "k_step_f32.hip",
+                os.path.join("..", "_build.py"), os.path.join("..", "..", "include", "octohydro.h"))
+
+
 def source_digest() -> str:
-    """sha256 over the library's HIP sources and headers, in name order."""
-    import glob
+    """sha256 over the substep kernel's sources, in the order listed."""
     import hashlib
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(KERNEL_DIR, "*.hip")) +
-                       glob.glob(os.path.join(KERNEL_DIR, "*.h"))):
-        with open(path, "rb") as f:
+    for name in STEP_SOURCES:
+        with open(os.path.join(KERNEL_DIR, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 

@@ -1,6 +1,6 @@
 // The 3D-reconstruction step kernel k_step3d: its instantiations for every
 // field count and both precisions live in this translation unit.
-#include "octohydro_kernels.h"
+#include "octohydro_kernels3d.h"
 
 namespace octohydro {
 

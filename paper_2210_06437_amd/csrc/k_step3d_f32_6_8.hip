@@ -1,7 +1,7 @@
 // Instantiations of the 3D step kernel k_step3d, binary32 storage, 6 to 8
 // fields: one of the units its instantiations are spread over so that they
 // compile in parallel.
-#include "octohydro_kernels.h"
+#include "octohydro_kernels3d.h"
 
 namespace octohydro {
 

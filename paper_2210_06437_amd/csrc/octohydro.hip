@@ -220,10 +220,20 @@ __global__ void k_validate(GridArgs g) {
     bool ok = kd == HYDRO_SAME_LEAF || kd == HYDRO_COARSER_LEAF || kd == HYDRO_SAME_REFINED;
     if (kd == HYDRO_SAME_REFINED) {
       ok = ok && id >= 0 && id < g.n_nodes;
+      // the children the 3-layer halo in this direction reads must exist:
+      // along an axis with offset +1 the low child, -1 the high child, 0
+      // both (the ghost fill and the restriction read them unchecked)
+      const int slot = (int)(i % 27);
+      const int r[3] = {slot % 3 - 1, (slot / 3) % 3 - 1, slot / 9 - 1};
       if (ok)
         for (int c = 0; c < 8; ++c) {
           const int ch = g.children[8 * id + c];
-          ok = ok && ch >= -1 && ch < g.n_leaves;
+          bool needed = true;
+          for (int k = 0; k < 3; ++k) {
+            const int bit = (c >> k) & 1;
+            needed = needed && (r[k] == 0 || bit == (r[k] > 0 ? 0 : 1));
+          }
+          ok = ok && ch >= -1 && ch < g.n_leaves && (!needed || ch >= 0);
         }
     } else {
       ok = ok && id >= 0 && id < g.n_leaves;

@@ -1,0 +1,390 @@
+// Device code of the full three-dimensional reconstruction with face
+// quadrature (HYDRO_RECON_3D): the line reconstruction, the 9-point face flux
+// and the k_step3d kernel with its launchers, on top of the method's shared
+// device code in octohydro_kernels.h.  Included by the k_step3d units only.
+#pragma once
+
+#include "octohydro_kernels.h"
+
+namespace octohydro {
+
+// ---------------------------------------------------------------------------
+// Full three-dimensional reconstruction with face quadrature (Sec. V-B-1: the
+// reconstruct kernel does a full 3D reconstruction, the flux kernel integrates
+// each face's flux by quadrature).
+//
+// Each cell gets values at its 26 face, edge and corner points: the point
+// t + p/2 (p in {-1,0,1}^3, not 0) comes from the PPM of the axis scheme on
+// the 5 cells t + m e, m = -2..2, with e = p or -p (first non-zero component
+// positive): the right end of the cell's parabola when e = p, else the left
+// end.  A face normal to D gets the Kurganov-Tadmor flux at its 9 points
+// (pu, pv) in {-1,0,1}^2 (u < v the other two axes) -- left state from the
+// left cell at (+1, pu, pv)/2, right state from the right cell at
+// (-1, pu, pv)/2 -- combined by the tensor Simpson rule
+//   ((corners + 4 edges) + 16 centre) / 36,
+//   corners = (H(-1,-1) + H(1,1)) + (H(1,-1) + H(-1,1)),
+//   edges   = (H(0,-1) + H(0,1)) + (H(-1,0) + H(1,0)).
+//
+// Ghost cells come from tiles materialised by k_fill (all 26 regions: the
+// diagonal lines reach edge and corner ghosts).
+// ---------------------------------------------------------------------------
+
+// One end of the PPM parabola of the cell at t along a line of tile stride s.
+template <typename T>
+__device__ __forceinline__ T line_end(const T* __restrict__ t, int s, bool right) {
+  const T q0 = t[-2 * s], q1 = t[-s], q2 = t[0], q3 = t[s], q4 = t[2 * s];
+  const T dm1 = limited_slope(q0, q1, q2);
+  const T dm2 = limited_slope(q1, q2, q3);
+  const T dm3 = limited_slope(q2, q3, q4);
+  T l = T(0.5) * (q1 + q2) - (dm2 - dm1) * T(1.0 / 6.0);
+  T r = T(0.5) * (q2 + q3) - (dm3 - dm2) * T(1.0 / 6.0);
+  monotonise(q2, l, r);
+  return right ? r : l;
+}
+
+// Tile stride of the line that gives point p, and whether p is its right end.
+struct PointLine {
+  int s;
+  bool right;
+};
+
+__device__ __forceinline__ constexpr PointLine point_line(int px, int py, int pz) {
+  return PointLine{((px != 0 ? px : (py != 0 ? py : pz)) > 0 ? 1 : -1) *
+                       (px + TW * py + TW * TW * pz),
+                   (px != 0 ? px : (py != 0 ? py : pz)) > 0};
+}
+
+// Point offset components of face point (pu, pv) on side sd (+1 left cell,
+// -1 right cell) of a face normal to D.
+template <int D>
+__device__ __forceinline__ constexpr PointLine face_point(int sd, int pu, int pv) {
+  return D == 0 ? point_line(sd, pu, pv) : (D == 1 ? point_line(pu, sd, pv)
+                                                   : point_line(pu, pv, sd));
+}
+
+// Simpson combination of the 9 point values of one field, points in the
+// order (-1,-1), (1,1), (1,-1), (-1,1), (0,-1), (0,1), (-1,0), (1,0), (0,0).
+template <typename T>
+__device__ __forceinline__ T simpson9(const T (&h)[9]) {
+  const T corners = (h[0] + h[1]) + (h[2] + h[3]);
+  const T edges = (h[4] + h[5]) + (h[6] + h[7]);
+  return ((corners + T(4) * edges) + T(16) * h[8]) / T(36);
+}
+
+// Flux of all fields through the face between tile cells tl and tl + stride
+// of D (Gt: field 0's tile of the leaf, field stride fsG).  The core fields'
+// end values at all 9 points are read first (their loads are independent, so
+// many are in flight at once) and give the points' Kurganov-Tadmor fluxes,
+// velocities and signal speeds; each passive field then uses those speeds.
+template <typename T, int NF, int D>
+__device__ __forceinline__ void face_flux_3d(const Phys<T>& ph, const T* __restrict__ Gt,
+                                             size_t fsG, int tl, T (&H)[NF], bool& bad) {
+  constexpr int SD = D == 0 ? 1 : (D == 1 ? TW : TW * TW);
+  constexpr int PU[9] = {-1, 1, 1, -1, 0, 0, -1, 1, 0};
+  constexpr int PV[9] = {-1, 1, -1, 1, -1, 1, 0, 0, 0};
+  const int tr = tl + SD;
+  T hc[NF_CORE][9], vl[9], vr[9], ha[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const PointLine pl = face_point<D>(1, PU[q], PV[q]);
+    const PointLine pr = face_point<D>(-1, PU[q], PV[q]);
+    T UL[NF_CORE], UR[NF_CORE], Hc[NF_CORE];
+#pragma unroll
+    for (int f = 0; f < NF_CORE; ++f) {
+      UL[f] = line_end(Gt + f * fsG + tl, pl.s, pl.right);
+      UR[f] = line_end(Gt + f * fsG + tr, pr.s, pr.right);
+    }
+    core_flux(ph, D, UL, UR, Hc, vl[q], vr[q], ha[q], bad);
+#pragma unroll
+    for (int f = 0; f < NF_CORE; ++f) hc[f][q] = Hc[f];
+  }
+#pragma unroll
+  for (int f = 0; f < NF_CORE; ++f) H[f] = simpson9(hc[f]);
+#pragma unroll
+  for (int f = NF_CORE; f < NF; ++f) {
+    T h[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const PointLine pl = face_point<D>(1, PU[q], PV[q]);
+      const PointLine pr = face_point<D>(-1, PU[q], PV[q]);
+      const T ul = line_end(Gt + f * fsG + tl, pl.s, pl.right);
+      const T ur = line_end(Gt + f * fsG + tr, pr.s, pr.right);
+      h[q] = T(0.5) * (ul * vl[q] + ur * vr[q]) - ha[q] * (ur - ul);
+    }
+    H[f] = simpson9(h);
+  }
+}
+
+// Face-neighbour register slots of the faces normal to axis D.
+__device__ __forceinline__ FaceNbr face_slots_3d(const GridArgs& g, int leaf, int D) {
+  FaceNbr fn;
+  fn.klo = fn.ilo = fn.khi = fn.ihi = 0;
+  fn.rlo = fn.rhi = fn.flo = fn.fhi = -1;
+  if (g.reg) {
+    fn.rlo = g.face_slot[6 * leaf + 2 * D];
+    fn.rhi = g.face_slot[6 * leaf + 2 * D + 1];
+    fn.flo = g.fine_slot[6 * leaf + 2 * D];
+    fn.fhi = g.fine_slot[6 * leaf + 2 * D + 1];
+  }
+  return fn;
+}
+
+// Tile index of leaf cell (x, y, z); -1 and 8 name the ghost layers.
+__device__ __forceinline__ constexpr int tile_at(int x, int y, int z) {
+  return (x + GH) + (y + GH) * TW + (z + GH) * TW * TW;
+}
+
+// One wave per leaf; lane (x, y) owns cell (x, y, z) of the current z-plane.
+// A face's flux depends on no other face, so each plane costs three face
+// evaluations per lane, each of them a wave-wide load of consecutive
+// x-cells: the cell's low x-face, its low y-face and its high z-face.  The
+// high x-face (y-face) of a cell is the low face of lane x+1 (y+1), taken by
+// a lane shuffle; for x = 7 (y = 7) it is face 8 of the row (column), which
+// a first pass evaluates for the whole leaf and keeps in LDS.  The low
+// z-face is the high z-face of the plane before (z-face 0 comes from the
+// first pass).  The differences are summed ((x + y) + z) in binary64 and the
+// cell is finished as k_step does.
+// binary64 runs at 1 wavefront per SIMD, two z-halves of three loops (one
+// face orientation per loop): one face evaluation nearly fills the 512
+// registers, and three of them in one loop body spilled 333 VGPRs to memory
+// (80 in this layout; 110.7 vs 122.3 ms on the 65535-leaf case).  binary32
+// runs at 2 wavefronts per SIMD (256 VGPRs; 63 ms vs 89 ms at 1) as one
+// sweep with the three faces in one loop body, whose LDS (11 KB) keeps 8
+// wavefronts per CU where the binary64 layout's 39 KB would allow 4.
+template <typename T, int NF>
+__global__ void __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1)
+    k_step3d(StepArgs s, const T* __restrict__ G) {
+  __shared__ double hx8[NF * 64];  // x-face 8 of row (y, z), at z * 8 + y
+  __shared__ double hy8[NF * 64];  // y-face 8 of column (x, z), at z * 8 + x
+  const GridArgs& g = s.g;
+  const int leaf = s.leaf_base + blockIdx.x;
+  if (leaf >= g.n_leaves) return;
+  const int lane = threadIdx.x;
+  LeafInfo li;
+  li.leaf = leaf;
+  const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
+  li.ix = c4.y;
+  li.iy = c4.z;
+  li.iz = c4.w;
+  li.blocks = g.base << c4.x;
+  const double dt = *s.dt;
+  const double inv_dx = (double)(SUB * li.blocks);
+  Phys<T> ph;
+  ph.gamma = (T)g.gamma;
+  ph.gm1 = (T)(g.gamma - 1.0);
+  ph.eta1 = (T)g.eta1;
+  const size_t fsG = (size_t)g.n_leaves * TILE;
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const T* __restrict__ Gt = G + (size_t)leaf * TILE;
+  const FaceNbr fx = face_slots_3d(g, leaf, 0);
+  const FaceNbr fy = face_slots_3d(g, leaf, 1);
+  const FaceNbr fz = face_slots_3d(g, leaf, 2);
+  const int x = lane & 7, y = lane >> 3;
+  bool bad = false;
+  const double dx = 1.0 / (double)(SUB * li.blocks);
+  const double rx = ((double)(SUB * li.ix + x) + 0.5) * dx - 0.5;
+  const double ry = ((double)(SUB * li.iy + y) + 0.5) * dx - 0.5;
+  if constexpr (sizeof(T) == 8) {
+  // binary64: two z-halves, each in three loops over its 4 planes -- x-faces,
+  // y-faces, z-faces -- so that one loop body holds one face evaluation.
+  // Lane (x, y) keeps its cells' dHx + dHy in its own LDS slots (acc3) and
+  // its low z-face flux in hz3.  The first half's loops start with a first
+  // pass (zl = -1): x-face 8 of every row and y-face 8 of every column into
+  // hx8/hy8, z-face 0 of the lane's column into hz3.
+  __shared__ double acc3[NF * 256];  // dHx + dHy of the half's cells, [f][zl * 64 + lane]
+  __shared__ double hz3[NF * 64];    // each lane's low z-face flux, [f][lane]
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    const int z0 = 4 * h, zs = h == 0 ? -1 : 0;
+#pragma unroll 1
+    for (int zl = zs; zl < 4; ++zl) {
+      wave_lds_sync();
+      const bool first = zl < 0;
+      const int z = z0 + zl;
+      T H[NF];
+      face_flux_3d<T, NF, 0>(ph, Gt, fsG, first ? tile_at(SUB - 1, x, y) : tile_at(x - 1, y, z),
+                             H, bad);
+      if (first) {
+        if (g.reg) record_face<T, NF>(g, fx, SUB, x, y, H);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) hx8[f * 64 + lane] = (double)H[f];
+        continue;
+      }
+      if (g.reg && x == 0) record_face<T, NF>(g, fx, 0, y, z, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double lo = (double)H[f];
+        const double up = __shfl_down(lo, 1, 8);  // lane x+1: its low face
+        const double hi = x == SUB - 1 ? hx8[f * 64 + z * 8 + y] : up;
+        acc3[f * 256 + zl * 64 + lane] = hi - lo;
+      }
+    }
+#pragma unroll 1
+    for (int zl = zs; zl < 4; ++zl) {
+      wave_lds_sync();
+      const bool first = zl < 0;
+      const int z = z0 + zl;
+      T H[NF];
+      face_flux_3d<T, NF, 1>(ph, Gt, fsG, first ? tile_at(x, SUB - 1, y) : tile_at(x, y - 1, z),
+                             H, bad);
+      if (first) {
+        if (g.reg) record_face<T, NF>(g, fy, SUB, x, y, H);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) hy8[f * 64 + lane] = (double)H[f];
+        continue;
+      }
+      if (g.reg && y == 0) record_face<T, NF>(g, fy, 0, x, z, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double lo = (double)H[f];
+        const double up = __shfl_down(lo, 8, 64);  // lane y+1: its low face
+        const double hi = y == SUB - 1 ? hy8[f * 64 + z * 8 + x] : up;
+        acc3[f * 256 + zl * 64 + lane] = acc3[f * 256 + zl * 64 + lane] + (hi - lo);
+      }
+    }
+#pragma unroll 1
+    for (int zl = zs; zl < 4; ++zl) {
+      const int z = z0 + zl;
+      T H[NF];
+      face_flux_3d<T, NF, 2>(ph, Gt, fsG, tile_at(x, y, z), H, bad);
+      if (zl < 0) {
+        if (g.reg) record_face<T, NF>(g, fz, 0, x, y, H);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) hz3[f * 64 + lane] = (double)H[f];
+        continue;
+      }
+      if (g.reg && z == SUB - 1) record_face<T, NF>(g, fz, SUB, x, y, H);
+      const T* __restrict__ ukc = Gt + tile_at(x, y, z);  // the cell's Uk
+      double src[4] = {0.0, 0.0, 0.0, 0.0};
+      const bool rot = g.omega != 0.0;
+      if (rot) {
+        const double rho = (double)ukc[0], sx = (double)ukc[fsG], sy = (double)ukc[2 * fsG];
+        const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+        src[0] = tw * sy + rho * om2 * rx;
+        src[1] = rho * om2 * ry - tw * sx;
+        src[3] = om2 * (sx * rx + sy * ry);
+      }
+      const uint32_t at = (uint32_t)leaf * CELLS + z * 64 + lane;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double sum = acc3[f * 256 + zl * 64 + lane] + ((double)H[f] - hz3[f * 64 + lane]);
+        hz3[f * 64 + lane] = (double)H[f];
+        const T u0 = s.U0 ? static_cast<const T*>(s.U0)[(size_t)f * fs + at] : T(0);
+        finish_cell<T>(s, (size_t)f * fs, at, ukc[f * fsG], u0, sum, rot && f >= 1 && f <= 4,
+                       f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+      }
+    }
+  }
+  } else {
+  // binary32: one sweep over the planes, three faces per plane in one loop
+  // body (at 2 wavefronts per SIMD the binary64 layout's 39 KB of LDS would
+  // halve the occupancy)
+  double Hz[NF];
+  // z = -1 is the first pass: x-face 8 of row (a, b) and y-face 8 of column
+  // (a, b), (a, b) = (lane & 7, lane >> 3), into LDS, and z-face 0 of the
+  // lane's column into Hz.  Each later z evaluates the three faces of the
+  // lane's cell and finishes it.
+#pragma unroll 1
+  for (int z = -1; z < SUB; ++z) {
+    wave_lds_sync();  // the first pass's LDS values are read from z = 0 on
+    const bool first = z < 0;
+    T H[NF];
+    double sxy[NF];
+    face_flux_3d<T, NF, 0>(ph, Gt, fsG, first ? tile_at(SUB - 1, x, y) : tile_at(x - 1, y, z),
+                           H, bad);
+    if (first) {
+      if (g.reg) record_face<T, NF>(g, fx, SUB, x, y, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) hx8[f * 64 + lane] = (double)H[f];
+    } else {
+      if (g.reg && x == 0) record_face<T, NF>(g, fx, 0, y, z, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double lo = (double)H[f];
+        const double up = __shfl_down(lo, 1, 8);  // lane x+1: its low face
+        const double hi = x == SUB - 1 ? hx8[f * 64 + z * 8 + y] : up;
+        sxy[f] = hi - lo;
+      }
+    }
+    face_flux_3d<T, NF, 1>(ph, Gt, fsG, first ? tile_at(x, SUB - 1, y) : tile_at(x, y - 1, z),
+                           H, bad);
+    if (first) {
+      if (g.reg) record_face<T, NF>(g, fy, SUB, x, y, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) hy8[f * 64 + lane] = (double)H[f];
+    } else {
+      if (g.reg && y == 0) record_face<T, NF>(g, fy, 0, x, z, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double lo = (double)H[f];
+        const double up = __shfl_down(lo, 8, 64);  // lane y+1: its low face
+        const double hi = y == SUB - 1 ? hy8[f * 64 + z * 8 + x] : up;
+        sxy[f] = sxy[f] + (hi - lo);
+      }
+    }
+    face_flux_3d<T, NF, 2>(ph, Gt, fsG, tile_at(x, y, z), H, bad);
+    if (first) {
+      if (g.reg) record_face<T, NF>(g, fz, 0, x, y, H);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) Hz[f] = (double)H[f];
+      continue;
+    }
+    if (g.reg && z == SUB - 1) record_face<T, NF>(g, fz, SUB, x, y, H);
+    const T* __restrict__ ukc = Gt + tile_at(x, y, z);  // the cell's Uk
+    double src[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool rot = g.omega != 0.0;
+    if (rot) {
+      const double rho = (double)ukc[0], sx = (double)ukc[fsG], sy = (double)ukc[2 * fsG];
+      const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+      src[0] = tw * sy + rho * om2 * rx;
+      src[1] = rho * om2 * ry - tw * sx;
+      src[3] = om2 * (sx * rx + sy * ry);
+    }
+    const uint32_t at = (uint32_t)leaf * CELLS + z * 64 + lane;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double sum = sxy[f] + ((double)H[f] - Hz[f]);
+      Hz[f] = (double)H[f];
+      const T u0 = s.U0 ? static_cast<const T*>(s.U0)[(size_t)f * fs + at] : T(0);
+      finish_cell<T>(s, (size_t)f * fs, at, ukc[f * fsG], u0, sum, rot && f >= 1 && f <= 4,
+                     f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+    }
+  }
+  }
+  if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
+}
+
+// Launch of k_step3d<T, NF>.  Its instantiations are explicit, spread over
+// the k_step3d_<precision>_<fields>.hip units, which compile in parallel.
+template <typename T, int NF>
+hipError_t launch_step3d_one(const StepArgs& a, int blocks, const T* G, hipStream_t st) {
+  hipLaunchKernelGGL((k_step3d<T, NF>), dim3(blocks), dim3(64), 0, st, a, G);
+  return hipGetLastError();
+}
+
+#define OCTOHYDRO_3D_EXTERN(T, n) \
+  extern template hipError_t launch_step3d_one<T, n>(const StepArgs&, int, const T*, hipStream_t);
+#define OCTOHYDRO_3D_EXTERN_ALL(T)                                                    \
+  OCTOHYDRO_3D_EXTERN(T, 6) OCTOHYDRO_3D_EXTERN(T, 7) OCTOHYDRO_3D_EXTERN(T, 8)       \
+  OCTOHYDRO_3D_EXTERN(T, 9) OCTOHYDRO_3D_EXTERN(T, 10) OCTOHYDRO_3D_EXTERN(T, 11)     \
+  OCTOHYDRO_3D_EXTERN(T, 12) OCTOHYDRO_3D_EXTERN(T, 13) OCTOHYDRO_3D_EXTERN(T, 14)    \
+  OCTOHYDRO_3D_EXTERN(T, 15) OCTOHYDRO_3D_EXTERN(T, 16)
+OCTOHYDRO_3D_EXTERN_ALL(double)
+OCTOHYDRO_3D_EXTERN_ALL(float)
+#undef OCTOHYDRO_3D_EXTERN_ALL
+#undef OCTOHYDRO_3D_EXTERN
+
+template <typename T>
+inline hipError_t launch_step3d_t(const StepArgs& a, int blocks, const T* G, hipStream_t st) {
+  switch (a.g.nf) {
+#define OCTOHYDRO_CASE3D(n) \
+  case n: return launch_step3d_one<T, n>(a, blocks, G, st);
+    OCTOHYDRO_CASE3D(6) OCTOHYDRO_CASE3D(7) OCTOHYDRO_CASE3D(8) OCTOHYDRO_CASE3D(9)
+    OCTOHYDRO_CASE3D(10) OCTOHYDRO_CASE3D(11) OCTOHYDRO_CASE3D(12) OCTOHYDRO_CASE3D(13)
+    OCTOHYDRO_CASE3D(14) OCTOHYDRO_CASE3D(15) OCTOHYDRO_CASE3D(16)
+#undef OCTOHYDRO_CASE3D
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace octohydro

@@ -80,23 +80,29 @@ def test_traffic_is_reported_only_for_the_measured_source(tmp_path, monkeypatch)
 
 
 def test_source_digest_covers_every_kernel_source(tmp_path, monkeypatch):
-    src = os.path.join(os.path.dirname(bench.__file__), "paper_2210_06437_amd", "csrc")
-    for name in os.listdir(src):
-        if not name.endswith((".hip", ".h")):
-            continue
-        d = tmp_path / "csrc"
-        if d.exists():
-            for f in d.iterdir():
-                f.unlink()
-        else:
-            d.mkdir()
-        for other in os.listdir(src):
-            if other.endswith((".hip", ".h")):
-                data = open(os.path.join(src, other), "rb").read()
-                if other == name:
-                    data += b"\n// changed\n"
-                (d / other).write_bytes(data)
-        monkeypatch.setattr(bench, "KERNEL_DIR", str(d))
-        changed = bench.source_digest()
+    """Changing any source the substep kernel is built from changes the
+    digest that gates the measured traffic."""
+    import shutil
+    pkg = os.path.join(os.path.dirname(bench.__file__), "paper_2210_06437_amd")
+    root = tmp_path / "repo"
+    (root / "paper_2210_06437_amd" / "csrc").mkdir(parents=True)
+    (root / "include").mkdir()
+    for name in bench.STEP_SOURCES:
+        src = os.path.normpath(os.path.join(pkg, "csrc", name))
+        dst = os.path.normpath(os.path.join(root, "paper_2210_06437_amd", "csrc", name))
+        shutil.copyfile(src, dst)
+    monkeypatch.setattr(bench, "KERNEL_DIR", str(root / "paper_2210_06437_amd" / "csrc"))
+    base = bench.source_digest()
+    assert base == bench.source_digest()
+    monkeypatch.undo()
+    assert base == bench.source_digest()  # the copy hashes like the tree
+    for name in bench.STEP_SOURCES:
+        path = os.path.normpath(os.path.join(root, "paper_2210_06437_amd", "csrc", name))
+        data = open(path, "rb").read()
+        with open(path, "ab") as f:
+            f.write(b"\n// changed\n")
+        monkeypatch.setattr(bench, "KERNEL_DIR", str(root / "paper_2210_06437_amd" / "csrc"))
+        assert bench.source_digest() != base, name
         monkeypatch.undo()
-        assert changed != bench.source_digest(), name
+        with open(path, "wb") as f:
+            f.write(data)

@@ -192,6 +192,34 @@ def test_validate_flag_rejects_a_corrupt_table_before_launch(env):
     assert e.value.code == hb.HYDRO_E_TABLE
 
 
+def test_validate_flag_checks_the_children_a_halo_reads(env):
+    """A valid uneven tree passes validation; the same table with a child the
+    halo of a refined neighbour reads set to -1 fails before any step kernel
+    reads it, while a child no halo reads may be -1."""
+    torch, hb = env
+    w = inputs.blobs(base=4, max_level=3)
+    grid, T, U = _setup(env, w)
+    dt = torch.tensor([1e-5], dtype=torch.float64, device="cuda")
+    out = grid.empty_state()
+    hb.hydro_step(grid, None, U, out, dt, 1.0, flags=hb.HYDRO_FLAG_VALIDATE)
+    kind, nbr = grid.host_kind, grid.host_nbr
+    leaf, slot = [int(v[0]) for v in np.nonzero(kind == hb.HYDRO_SAME_REFINED)]
+    node = int(nbr[leaf, slot])
+    r = [slot % 3 - 1, (slot // 3) % 3 - 1, slot // 9 - 1]
+    need = [c for c in range(8) if all(r[k] == 0 or ((c >> k) & 1) == (0 if r[k] > 0 else 1)
+                                       for k in range(3))]
+    saved = grid.children[node].clone()
+    try:
+        grid.children[node, need[0]] = -1
+        grid.status.zero_()
+        with pytest.raises(hb.HydroError) as e:
+            hb.hydro_step(grid, None, U, out, dt, 1.0, flags=hb.HYDRO_FLAG_VALIDATE)
+        assert e.value.code == hb.HYDRO_E_TABLE
+    finally:
+        grid.children[node] = saved
+        grid.status.zero_()
+
+
 def test_fp32_mixed_l1_error_against_fp64_oracle(env):
     torch, hb = env
     w = inputs.sod(base=4, steps=10)
