@@ -158,13 +158,15 @@ def time_rk3_with(torch, hb, w, steps, warmup, **grid_kw):
     return ms, slots
 
 
-def time_rk3_3d(torch, hb, w, steps, warmup):
-    """FP64 RK3 steps with the full 3D reconstruction (HIP graph), and the
-    3D substep kernel alone in its later-stage form (events; the ghosted
-    tiles of the input are made once and reused with NODES_READY)."""
-    grid = hb.Grid(w.leaf_coord, w.base, w.nf, hb.HYDRO_F64, reconstruction=hb.HYDRO_RECON_3D,
+def time_rk3_3d(torch, hb, w, steps, warmup, dtype=None):
+    """RK3 steps with the full 3D reconstruction (HIP graph), and the 3D
+    substep kernel alone in its later-stage form (events; the ghosted tiles
+    of the input are made once and reused with NODES_READY)."""
+    dtype = hb.HYDRO_F64 if dtype is None else dtype
+    grid = hb.Grid(w.leaf_coord, w.base, w.nf, dtype, reconstruction=hb.HYDRO_RECON_3D,
                    cfl_epilogue=True)
-    A = torch.from_numpy(w.U).to("cuda").contiguous()
+    tdt = torch.float64 if dtype == hb.HYDRO_F64 else torch.float32
+    A = torch.from_numpy(w.U).to("cuda").to(tdt).contiguous()
     B, W1, W2 = grid.empty_state(), grid.empty_state(), grid.empty_state()
     dt = torch.zeros(2, dtype=torch.float64, device="cuda")
     hb.hydro_cfl_dt(grid, A, 0.0, dt[1:])
@@ -478,10 +480,17 @@ def main():
         ops3 = ops_per_leaf_stage_3d(nf, True) * n
         recon3d = {"value": cells / (ms3 * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms3,
                    "steps": steps3,
-                   "kernel": "k_step3d<double,11> (3D reconstruction, 9-point Simpson flux)",
+                   "kernel": "k_step3d_wg<double,11> (3D reconstruction, 9-point Simpson flux, "
+                             "one workgroup per leaf)",
                    "kernel_ms": kms3, "ghost_fill_ms": fill3, "ops_per_launch": ops3,
                    "alu_frac": ops3 / (kms3 * 1e-3) / ALU_PEAK,
                    "hbm_frac": hbm_bytes_per_leaf_stage(nf, 8, True) * n / (kms3 * 1e-3) / HBM_PEAK}
+        if not args.no_fp32:
+            log(f"FP32-mixed full 3D reconstruction: 1 warmup + {steps3} timed RK3 steps")
+            ms3f, kms3f, fill3f = time_rk3_3d(torch, hb, w, steps3, 1, hb.HYDRO_F32)
+            recon3d["fp32_mixed"] = {
+                "value": cells / (ms3f * 1e-3), "ms_per_step": ms3f, "kernel_ms": kms3f,
+                "ghost_fill_ms": fill3f, "alu_frac": ops3 / (kms3f * 1e-3) / ALU_PEAK}
 
     # the method's optional terms on the same workload: coarse-fine flux
     # correction (recorded face fluxes + one k_reflux launch per face

@@ -362,6 +362,10 @@ const char* hydro_last_error(void);
  *                             node_state2_dev lets its substeps leave the
  *                             node copies of their outputs (1) or makes
  *                             them in a pass before each substep (0)
+ *   HYDRO_OPT_3D_WORKGROUP    1 or 0: the 3D step with one 256-thread
+ *                             workgroup per leaf (where its face fluxes fit
+ *                             in LDS: binary64 up to 11 fields, binary32 up
+ *                             to 16) or one wavefront per leaf
  * Every choice computes the same bits.  Options are process-wide and take effect at the next launch (a captured
  * graph keeps the kernel it was captured with).  Host only, thread-safe.
  */
@@ -370,6 +374,7 @@ const char* hydro_last_error(void);
 #define HYDRO_OPT_WAVES_PER_LEAF 3
 #define HYDRO_OPT_CFL_EPILOGUE 4
 #define HYDRO_OPT_FUSED_RESTRICT 5
+#define HYDRO_OPT_3D_WORKGROUP 6
 int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t value);
 int hydro_get_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t* value);
 

@@ -44,6 +44,7 @@ EXPORTS = [
 HYDRO_OPT_WAVES_PER_SIMD, HYDRO_OPT_XCD_REMAP, HYDRO_OPT_WAVES_PER_LEAF = 1, 2, 3
 HYDRO_OPT_CFL_EPILOGUE = 4
 HYDRO_OPT_FUSED_RESTRICT = 5
+HYDRO_OPT_3D_WORKGROUP = 6
 
 
 class HydroError(RuntimeError):

@@ -5,8 +5,11 @@
 
 namespace octohydro {
 
-template hipError_t launch_step3d_one<float, 12>(const StepArgs&, int, const float*, hipStream_t);
-template hipError_t launch_step3d_one<float, 13>(const StepArgs&, int, const float*, hipStream_t);
-template hipError_t launch_step3d_one<float, 14>(const StepArgs&, int, const float*, hipStream_t);
+template hipError_t launch_step3d_one<float, 12>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<float, 13>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<float, 14>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
 
 }  // namespace octohydro

@@ -5,7 +5,9 @@
 
 namespace octohydro {
 
-template hipError_t launch_step3d_one<float, 15>(const StepArgs&, int, const float*, hipStream_t);
-template hipError_t launch_step3d_one<float, 16>(const StepArgs&, int, const float*, hipStream_t);
+template hipError_t launch_step3d_one<float, 15>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<float, 16>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
 
 }  // namespace octohydro

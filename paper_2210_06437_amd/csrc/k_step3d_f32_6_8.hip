@@ -5,8 +5,11 @@
 
 namespace octohydro {
 
-template hipError_t launch_step3d_one<float, 6>(const StepArgs&, int, const float*, hipStream_t);
-template hipError_t launch_step3d_one<float, 7>(const StepArgs&, int, const float*, hipStream_t);
-template hipError_t launch_step3d_one<float, 8>(const StepArgs&, int, const float*, hipStream_t);
+template hipError_t launch_step3d_one<float, 6>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<float, 7>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<float, 8>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
 
 }  // namespace octohydro

@@ -5,8 +5,11 @@
 
 namespace octohydro {
 
-template hipError_t launch_step3d_one<float, 9>(const StepArgs&, int, const float*, hipStream_t);
-template hipError_t launch_step3d_one<float, 10>(const StepArgs&, int, const float*, hipStream_t);
-template hipError_t launch_step3d_one<float, 11>(const StepArgs&, int, const float*, hipStream_t);
+template hipError_t launch_step3d_one<float, 9>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<float, 10>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<float, 11>(const StepArgs&, int, const float*, int,
+                                     hipStream_t);
 
 }  // namespace octohydro

@@ -5,8 +5,11 @@
 
 namespace octohydro {
 
-template hipError_t launch_step3d_one<double, 12>(const StepArgs&, int, const double*, hipStream_t);
-template hipError_t launch_step3d_one<double, 13>(const StepArgs&, int, const double*, hipStream_t);
-template hipError_t launch_step3d_one<double, 14>(const StepArgs&, int, const double*, hipStream_t);
+template hipError_t launch_step3d_one<double, 12>(const StepArgs&, int, const double*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<double, 13>(const StepArgs&, int, const double*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<double, 14>(const StepArgs&, int, const double*, int,
+                                     hipStream_t);
 
 }  // namespace octohydro

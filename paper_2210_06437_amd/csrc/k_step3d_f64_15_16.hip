@@ -5,7 +5,9 @@
 
 namespace octohydro {
 
-template hipError_t launch_step3d_one<double, 15>(const StepArgs&, int, const double*, hipStream_t);
-template hipError_t launch_step3d_one<double, 16>(const StepArgs&, int, const double*, hipStream_t);
+template hipError_t launch_step3d_one<double, 15>(const StepArgs&, int, const double*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<double, 16>(const StepArgs&, int, const double*, int,
+                                     hipStream_t);
 
 }  // namespace octohydro

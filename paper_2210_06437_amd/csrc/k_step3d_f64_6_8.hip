@@ -5,8 +5,11 @@
 
 namespace octohydro {
 
-template hipError_t launch_step3d_one<double, 6>(const StepArgs&, int, const double*, hipStream_t);
-template hipError_t launch_step3d_one<double, 7>(const StepArgs&, int, const double*, hipStream_t);
-template hipError_t launch_step3d_one<double, 8>(const StepArgs&, int, const double*, hipStream_t);
+template hipError_t launch_step3d_one<double, 6>(const StepArgs&, int, const double*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<double, 7>(const StepArgs&, int, const double*, int,
+                                     hipStream_t);
+template hipError_t launch_step3d_one<double, 8>(const StepArgs&, int, const double*, int,
+                                     hipStream_t);
 
 }  // namespace octohydro

@@ -337,17 +337,65 @@ static int grid_blocks(int64_t work, int threads, int cap) {
   return (int)(b < 1 ? 1 : b);
 }
 
+// Ghost fill (hydro_fill_ghosts) into materialised tiles.
+// One workgroup per leaf: each thread takes tile cells t, t + 256, ..., works
+// out where the cell's value comes from once (the leaf itself, a same-level
+// or coarser leaf, or the 8 cells of a refined neighbour's child) and copies
+// or restricts that source in every field.  Consecutive threads hold
+// consecutive tile cells, so a wavefront's writes and most of its reads are
+// contiguous rows.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill(GridArgs g, const T* __restrict__ U,
+                                              T* __restrict__ G) {
+  const int leaf = blockIdx.x;
+  const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
+  const int ic[3] = {c4.y, c4.z, c4.w};
+  const int blocks = g.base << c4.x;
+  const size_t fsU = (size_t)g.n_leaves * CELLS, fsG = (size_t)g.n_leaves * TILE;
+  T* __restrict__ Gl = G + (size_t)leaf * TILE;
+  for (int t = threadIdx.x; t < TILE; t += blockDim.x) {
+    const int tp[3] = {t % TW, (t / TW) % TW, t / (TW * TW)};
+    int r[3], l[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      r[k] = tp[k] < GH ? -1 : (tp[k] >= GH + SUB ? 1 : 0);
+      l[k] = tp[k] - GH - SUB * r[k];
+    }
+    const int slot = (r[2] + 1) * 9 + (r[1] + 1) * 3 + (r[0] + 1);
+    const int kind = slot == 13 ? (int)HYDRO_SAME_LEAF : (int)g.kind[27 * leaf + slot];
+    const int id = slot == 13 ? leaf : g.nbr[27 * leaf + slot];
+    if (kind == HYDRO_SAME_REFINED) {
+      for (int f = 0; f < g.nf; ++f)
+        Gl[f * fsG + t] = neighbour_value<T>(g, U + f * fsU, leaf, ic, blocks, kind, id, r, l);
+    } else {
+      // a copy: the cell itself, a same-level cell or the covering coarse cell
+      const T* __restrict__ src = U;
+      size_t o;
+      if (kind == HYDRO_SAME_LEAF) {
+        o = (size_t)id * CELLS + l[2] * 64 + l[1] * 8 + l[0];
+      } else {
+        int c[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int nb = wrap(ic[k] + r[k], blocks);
+          c[k] = 4 * (nb & 1) + (l[k] >> 1);
+        }
+        o = (size_t)id * CELLS + c[2] * 64 + c[1] * 8 + c[0];
+      }
+      for (int f = 0; f < g.nf; ++f) Gl[f * fsG + t] = src[f * fsU + o];
+    }
+  }
+}
+
 // Ghosted 14^3 tiles of U into G (all 26 ghost regions).
 static int fill_launch(const hydro_grid* gr, const void* U, void* G, hipStream_t st) {
   const GridArgs g = grid_args(gr);
-  const int64_t total = (int64_t)g.nf * g.n_leaves * TILE;
-  const int blocks = grid_blocks(total, 256, 1 << 16);
   if (gr->dtype == HYDRO_F64)
-    hipLaunchKernelGGL(k_fill<double>, dim3(blocks), dim3(256), 0, st, g,
-                       static_cast<const double*>(U), static_cast<double*>(G), total);
+    hipLaunchKernelGGL(k_fill<double>, dim3(g.n_leaves), dim3(256), 0, st, g,
+                       static_cast<const double*>(U), static_cast<double*>(G));
   else
-    hipLaunchKernelGGL(k_fill<float>, dim3(blocks), dim3(256), 0, st, g,
-                       static_cast<const float*>(U), static_cast<float*>(G), total);
+    hipLaunchKernelGGL(k_fill<float>, dim3(g.n_leaves), dim3(256), 0, st, g,
+                       static_cast<const float*>(U), static_cast<float*>(G));
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
@@ -376,6 +424,7 @@ struct Options {
   int waves_per_leaf = 1;
   int cfl_epilogue = 1;
   int fused_restrict = 1;
+  int recon3d_wg = 1;
 };
 static Options g_opts[2][17];
 static std::mutex g_opts_mu;
@@ -494,7 +543,8 @@ static int substep_kernels(const hydro_grid* gr, const StepArgs& a, int blocks, 
   int rc;
   if (gr->reconstruction == HYDRO_RECON_3D) {
     if (pre && (rc = fill_launch(gr, a.Uk, gr->ghost_tile_dev, st))) return rc;
-    HIP_TRY(launch_step3d(a, gr->dtype, blocks, gr->ghost_tile_dev, st));
+    HIP_TRY(launch_step3d(a, gr->dtype, blocks, gr->ghost_tile_dev,
+                          get_options(gr->dtype, gr->n_fields).recon3d_wg, st));
     return HYDRO_OK;
   }
   if (pre && (rc = restrict_launch(gr, a.Uk, st))) return rc;
@@ -659,6 +709,11 @@ int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t va
                     "hydro_set_option: remap is 0, 1 or a power of two in [2, 4096]");
       o.xcd_remap = value;
       return HYDRO_OK;
+    case HYDRO_OPT_3D_WORKGROUP:
+      if (value != 0 && value != 1)
+        return fail(HYDRO_E_ARG, "hydro_set_option: 3D workgroup form is 0 or 1");
+      o.recon3d_wg = value;
+      return HYDRO_OK;
     case HYDRO_OPT_FUSED_RESTRICT:
       if (value != 0 && value != 1)
         return fail(HYDRO_E_ARG, "hydro_set_option: fused restriction is 0 or 1");
@@ -691,6 +746,7 @@ int hydro_get_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t* v
   else if (option == HYDRO_OPT_WAVES_PER_LEAF) *value = o.waves_per_leaf;
   else if (option == HYDRO_OPT_CFL_EPILOGUE) *value = o.cfl_epilogue;
   else if (option == HYDRO_OPT_FUSED_RESTRICT) *value = o.fused_restrict;
+  else if (option == HYDRO_OPT_3D_WORKGROUP) *value = o.recon3d_wg;
   else return fail(HYDRO_E_ARG, "hydro_get_option: unknown option %d", option);
   return HYDRO_OK;
 }

@@ -101,38 +101,6 @@ __device__ __forceinline__ T neighbour_value(const GridArgs& g, const T* __restr
   return T(0.125) * (((v000 + v100) + (v010 + v110)) + ((v001 + v101) + (v011 + v111)));
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
-    k_fill(GridArgs g, const T* __restrict__ U, T* __restrict__ G, int64_t total) {
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int t = (int)(idx % TILE);
-    const int64_t fl = idx / TILE;
-    const int leaf = (int)(fl % g.n_leaves);
-    const int f = (int)(fl / g.n_leaves);
-    const int tp[3] = {t % TW, (t / TW) % TW, t / (TW * TW)};
-    int r[3], l[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      r[k] = tp[k] < GH ? -1 : (tp[k] >= GH + SUB ? 1 : 0);
-      l[k] = tp[k] - GH - SUB * r[k];
-    }
-    const T* __restrict__ Uf = U + (size_t)f * g.n_leaves * CELLS;
-    const int slot = (r[2] + 1) * 9 + (r[1] + 1) * 3 + (r[0] + 1);
-    T v;
-    if (slot == 13) {
-      v = Uf[(size_t)leaf * CELLS + l[2] * 64 + l[1] * 8 + l[0]];
-    } else {
-      const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
-      const int ic[3] = {c4.y, c4.z, c4.w};
-      const int blocks = g.base << c4.x;
-      v = neighbour_value<T>(g, Uf, leaf, ic, blocks, g.kind[27 * leaf + slot],
-                             g.nbr[27 * leaf + slot], r, l);
-    }
-    G[idx] = v;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Restricted copies of the refined nodes (the coarse side of a coarse-fine
 // face, Sec. VI): coarse cell (x, y, z) of node n is the mean of the 8 cells
@@ -1335,6 +1303,7 @@ hipError_t launch_step_f64_cfl(const StepArgs& a, int blocks, StepShape sh, hipS
 hipError_t launch_step_f32_cfl(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
 hipError_t launch_step_f64_restrict(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
 hipError_t launch_step_f32_restrict(const StepArgs& a, int blocks, StepShape sh, hipStream_t st);
-hipError_t launch_step3d(const StepArgs& a, int dtype, int blocks, const void* G, hipStream_t st);
+hipError_t launch_step3d(const StepArgs& a, int dtype, int blocks, const void* G, int wg,
+                         hipStream_t st);
 
 }  // namespace octohydro

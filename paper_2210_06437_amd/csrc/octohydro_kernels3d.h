@@ -356,14 +356,158 @@ __global__ void __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1)
 
 // Launch of k_step3d<T, NF>.  Its instantiations are explicit, spread over
 // the k_step3d_<precision>_<fields>.hip units, which compile in parallel.
+// ---------------------------------------------------------------------------
+// The 3D step with one 256-thread workgroup (4 wavefronts) per leaf.  The
+// leaf's face fluxes are 27 planes of 64 faces: the low x-faces of each of
+// the 8 cell planes (lane (x, y): face between cells x - 1 and x), the low
+// y-faces of each plane, the 9 planes of z-faces (between cell planes z - 1
+// and z), and the leaf's high x- and y-faces (lane (y, z) and (x, z)).  The
+// wavefronts take these face planes in turn (wavefront w evaluates planes
+// w, w + 4, ...), keep every flux in LDS, and after one workgroup barrier
+// all 256 threads finish the 512 cells.  One leaf per CU keeps the tile
+// planes its wavefronts read at once in the XCD's L2.  Each face is the
+// same face_flux_3d evaluation as in k_step3d and each cell the same sums
+// ((dHx + dHy) + dHz), so the results are bit-identical to it.
+// ---------------------------------------------------------------------------
+
+// Face plane j of the task list: direction and plane, in an order that
+// keeps the four wavefronts on neighbouring cell planes.
+struct FacePlane {
+  int d, p;  // d: 0 x, 1 y, 2 z; p: cell plane (x, y: 0..7, 8 = the high
+             // boundary face) or z-face plane 0..8
+};
+
+__device__ __forceinline__ FacePlane face_plane(int j) {
+  // x8, y8, then (z0), and per cell plane p: x p, y p, z p+1
+  if (j == 0) return FacePlane{0, 8};
+  if (j == 1) return FacePlane{1, 8};
+  if (j == 2) return FacePlane{2, 0};
+  const int k = j - 3, p = k / 3, r = k % 3;
+  return r == 0 ? FacePlane{0, p} : (r == 1 ? FacePlane{1, p} : FacePlane{2, p + 1});
+}
+constexpr int FACE_PLANES = 27;
+
+// LDS bytes of k_step3d_wg's flux store: 8 + 8 + 9 + 2 planes of 64 faces.
 template <typename T, int NF>
-hipError_t launch_step3d_one(const StepArgs& a, int blocks, const T* G, hipStream_t st) {
+constexpr size_t wg3d_lds_bytes() {
+  return (size_t)FACE_PLANES * 64 * NF * sizeof(T);
+}
+
+template <typename T, int NF>
+__global__ void __launch_bounds__(256, 1) k_step3d_wg(StepArgs s, const T* __restrict__ G) {
+  // fluxes, [plane][field][lane]: planes 0-7 low x-faces, 8 high x-faces,
+  // 9-16 low y-faces, 17 high y-faces, 18-26 z-faces 0..8
+  __shared__ T Hs[FACE_PLANES][NF][64];
+  const GridArgs& g = s.g;
+  const int leaf = s.leaf_base + blockIdx.x;
+  if (leaf >= g.n_leaves) return;  // uniform over the workgroup
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
+  const int blocks = g.base << c4.x;
+  Phys<T> ph;
+  ph.gamma = (T)g.gamma;
+  ph.gm1 = (T)(g.gamma - 1.0);
+  ph.eta1 = (T)g.eta1;
+  const size_t fsG = (size_t)g.n_leaves * TILE;
+  const T* __restrict__ Gt = G + (size_t)leaf * TILE;
+  const int a = lane & 7, b = lane >> 3;
+  bool bad = false;
+#pragma unroll 1
+  for (int j = wave; j < FACE_PLANES; j += 4) {
+    const FacePlane fp = face_plane(j);
+    T H[NF];
+    int slot;
+    if (fp.d == 0) {
+      // lane (a, b) = (x, y) of a low face in plane p, or (y, z) of face 8
+      const bool hi = fp.p == SUB;
+      face_flux_3d<T, NF, 0>(ph, Gt, fsG, hi ? tile_at(SUB - 1, a, b) : tile_at(a - 1, b, fp.p),
+                             H, bad);
+      if (g.reg) {
+        const FaceNbr fn = face_slots_3d(g, leaf, 0);
+        if (hi) record_face<T, NF>(g, fn, SUB, a, b, H);
+        else if (a == 0) record_face<T, NF>(g, fn, 0, b, fp.p, H);
+      }
+      slot = hi ? SUB : fp.p;
+    } else if (fp.d == 1) {
+      const bool hi = fp.p == SUB;
+      face_flux_3d<T, NF, 1>(ph, Gt, fsG, hi ? tile_at(a, SUB - 1, b) : tile_at(a, b - 1, fp.p),
+                             H, bad);
+      if (g.reg) {
+        const FaceNbr fn = face_slots_3d(g, leaf, 1);
+        if (hi) record_face<T, NF>(g, fn, SUB, a, b, H);
+        else if (b == 0) record_face<T, NF>(g, fn, 0, a, fp.p, H);
+      }
+      slot = 9 + (hi ? SUB : fp.p);
+    } else {
+      face_flux_3d<T, NF, 2>(ph, Gt, fsG, tile_at(a, b, fp.p - 1), H, bad);
+      if (g.reg && (fp.p == 0 || fp.p == SUB))
+        record_face<T, NF>(g, face_slots_3d(g, leaf, 2), fp.p, a, b, H);
+      slot = 18 + fp.p;
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) Hs[slot][f][lane] = H[f];
+  }
+  if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
+  __syncthreads();
+
+  // finish the leaf's cells: thread t takes cells t and t + 256
+  const double dt = *s.dt;
+  const double inv_dx = (double)(SUB * blocks);
+  const double dx = 1.0 / (double)(SUB * blocks);
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const T* __restrict__ Uk = static_cast<const T*>(s.Uk);
+  const T* __restrict__ U0 = static_cast<const T*>(s.U0);
+#pragma unroll 1
+  for (int c = threadIdx.x; c < CELLS; c += 256) {
+    const int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+    const int xy = y * 8 + x;
+    const uint32_t at = (uint32_t)leaf * CELLS + c;
+    double src[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool rot = g.omega != 0.0;
+    if (rot) {
+      const double rx = ((double)(SUB * c4.y + x) + 0.5) * dx - 0.5;
+      const double ry = ((double)(SUB * c4.z + y) + 0.5) * dx - 0.5;
+      const double rho = (double)Uk[at], sx = (double)Uk[fs + at], sy = (double)Uk[2 * fs + at];
+      const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+      src[0] = tw * sy + rho * om2 * rx;
+      src[1] = rho * om2 * ry - tw * sx;
+      src[3] = om2 * (sx * rx + sy * ry);
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double xlo = (double)Hs[z][f][xy];
+      const double xhi = (double)(x == SUB - 1 ? Hs[SUB][f][z * 8 + y] : Hs[z][f][xy + 1]);
+      const double ylo = (double)Hs[9 + z][f][xy];
+      const double yhi = (double)(y == SUB - 1 ? Hs[9 + SUB][f][z * 8 + x] : Hs[9 + z][f][xy + 8]);
+      const double zlo = (double)Hs[18 + z][f][xy];
+      const double zhi = (double)Hs[18 + z + 1][f][xy];
+      const double sum = ((xhi - xlo) + (yhi - ylo)) + (zhi - zlo);
+      const T u0 = U0 ? U0[(size_t)f * fs + at] : T(0);
+      finish_cell<T>(s, (size_t)f * fs, at, Uk[(size_t)f * fs + at], u0, sum,
+                     rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+    }
+  }
+}
+
+// Launch of the 3D step: the workgroup-per-leaf form where its flux store
+// fits in LDS (binary64 up to 11 fields, binary32 up to 16) unless the
+// one-wavefront form is asked for (wg == 0), else k_step3d.
+template <typename T, int NF>
+hipError_t launch_step3d_one(const StepArgs& a, int blocks, const T* G, int wg, hipStream_t st) {
+  if constexpr (wg3d_lds_bytes<T, NF>() <= 160 * 1024) {
+    if (wg) {
+      hipLaunchKernelGGL((k_step3d_wg<T, NF>), dim3(blocks), dim3(256), 0, st, a, G);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_step3d<T, NF>), dim3(blocks), dim3(64), 0, st, a, G);
   return hipGetLastError();
 }
 
 #define OCTOHYDRO_3D_EXTERN(T, n) \
-  extern template hipError_t launch_step3d_one<T, n>(const StepArgs&, int, const T*, hipStream_t);
+  extern template hipError_t launch_step3d_one<T, n>(const StepArgs&, int, const T*, int, \
+                                                     hipStream_t);
 #define OCTOHYDRO_3D_EXTERN_ALL(T)                                                    \
   OCTOHYDRO_3D_EXTERN(T, 6) OCTOHYDRO_3D_EXTERN(T, 7) OCTOHYDRO_3D_EXTERN(T, 8)       \
   OCTOHYDRO_3D_EXTERN(T, 9) OCTOHYDRO_3D_EXTERN(T, 10) OCTOHYDRO_3D_EXTERN(T, 11)     \
@@ -375,10 +519,11 @@ OCTOHYDRO_3D_EXTERN_ALL(float)
 #undef OCTOHYDRO_3D_EXTERN
 
 template <typename T>
-inline hipError_t launch_step3d_t(const StepArgs& a, int blocks, const T* G, hipStream_t st) {
+inline hipError_t launch_step3d_t(const StepArgs& a, int blocks, const T* G, int wg,
+                                  hipStream_t st) {
   switch (a.g.nf) {
 #define OCTOHYDRO_CASE3D(n) \
-  case n: return launch_step3d_one<T, n>(a, blocks, G, st);
+  case n: return launch_step3d_one<T, n>(a, blocks, G, wg, st);
     OCTOHYDRO_CASE3D(6) OCTOHYDRO_CASE3D(7) OCTOHYDRO_CASE3D(8) OCTOHYDRO_CASE3D(9)
     OCTOHYDRO_CASE3D(10) OCTOHYDRO_CASE3D(11) OCTOHYDRO_CASE3D(12) OCTOHYDRO_CASE3D(13)
     OCTOHYDRO_CASE3D(14) OCTOHYDRO_CASE3D(15) OCTOHYDRO_CASE3D(16)

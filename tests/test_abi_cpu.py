@@ -161,7 +161,7 @@ def test_launch_options_roundtrip_and_validation(hb):
     # or a power of two up to 4096
     for bad in ((0, 6, 1, 3), (0, 5, 1, 1), (2, 6, 1, 1), (0, 6, 9, 1), (1, 17, 2, 1),
                 (0, 6, 2, 5), (0, 6, 2, -1), (0, 6, 2, 8192), (0, 6, 3, 2), (1, 11, 3, 3),
-                (0, 11, 3, 0), (0, 11, 4, 2), (0, 11, 5, 3)):
+                (0, 11, 3, 0), (0, 11, 4, 2), (0, 11, 5, 3), (1, 11, 6, 2)):
         with pytest.raises(hb.HydroError) as e:
             hb.hydro_set_option(*bad)
         assert e.value.code == hb.HYDRO_E_ARG

@@ -347,7 +347,7 @@ def test_uneven_octree_22k_leaves_sampled(env):
 
 def test_turbulence_65k_leaves_sampled(env):
     w = inputs.config5()
-    _sampled_rk3(env, w, 32, 5)
+    _sampled_rk3(env, w, 160, 5)
 
 
 @pytest.mark.parametrize("nf", [7, 11, 16])

@@ -165,3 +165,72 @@ def test_fp32_mixed_3d_l1_error(env, recon3d):
     assert np.all(l1[[0, 1, 2, 4, 5]] < 1e-5), l1
     assert np.all(l1[6:] < 1e-5), l1
     assert l1[3] < 1e-3, l1  # s_z: starts at zero (planar orbits), so it is small
+
+
+def test_sampled_leaves_of_the_turbulence_workload_3d(env, recon3d):
+    """The benchmark's 65535-leaf workload in the 3D mode: one later-stage
+    substep (reads U0) on the whole tree, with the launch shape the bench
+    times, checked on sampled leaves of both levels and on leaves next to
+    refined blocks, which the oracle recomputes one by one."""
+    torch, hb = env
+    w = inputs.config5()
+    print(f"case config5 3D sampled: {w.n_leaves} leaves", flush=True)
+    grid, T, U = _grid(env, w)
+    dt0 = 0.5 * oracle.cfl_dt(T, w.U, 0.4)
+    dt = torch.tensor([dt0], dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(2210064375)
+    # U0: the input scaled, so that the stage combination is exercised
+    U0h = w.U * 1.001
+    U0 = torch.from_numpy(U0h).to("cuda")
+    out = grid.empty_state()
+    hb.hydro_step(grid, U0, U, out, dt, 0.25)
+    torch.cuda.synchronize()
+    assert hb.hydro_check_status(grid) == hb.HYDRO_OK
+    lev = w.leaf_coord[:, 0]
+    near = np.nonzero((T.kind == oracle.SAME_REFINED).any(1))[0]
+    pick = np.unique(np.concatenate([
+        rng.choice(np.flatnonzero(lev == 0), 24, replace=False),
+        rng.choice(np.flatnonzero(lev == 1), 24, replace=False),
+        rng.choice(near, 16, replace=False)]).astype(np.int32))
+    ref, bad = oracle.step_subset(T, w.U, dt0, pick, beta=0.25, U0=U0h)
+    assert bad == 0
+    got = out.cpu().numpy()[:, pick]
+    err = _rel(got, ref[:, pick])
+    print(f"  {len(pick)} sampled leaves: rel err {err.max():.3e} "
+          f"bit-exact {np.array_equal(got, ref[:, pick])}")
+    assert np.all(err <= TOL64), err
+
+
+@pytest.mark.parametrize("dtype,nf", [(0, 11), (0, 6), (0, 14), (1, 11), (1, 16)])
+def test_workgroup_and_wavefront_forms_give_the_same_bits(env, recon3d, dtype, nf):
+    """The 3D step with one workgroup per leaf (face fluxes in LDS) and with
+    one wavefront per leaf: the same bits, with the flux correction and the
+    rotating frame on (binary64 beyond 11 fields has only the wavefront
+    form); binary64 also against the oracle."""
+    torch, hb = env
+    w = inputs.blobs(base=2, max_level=2, threshold=0.5)
+    rng = np.random.default_rng(nf)
+    extra = [w.U[0] * rng.uniform(0.1, 0.3, size=w.U[0].shape) for _ in range(nf - 6)]
+    w.U = np.ascontiguousarray(np.concatenate([w.U[:6], np.stack(extra)]) if nf > 6 else w.U[:6])
+    print(f"case amr-base2 3D forms dtype={dtype} nf={nf}: {w.n_leaves} leaves", flush=True)
+    grid, T, U = _grid(env, w, dtype=dtype, reflux=True, omega=0.7)
+    old = hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_3D_WORKGROUP)
+    outs = []
+    try:
+        for form in (1, 0):
+            hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_3D_WORKGROUP, form)
+            W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
+            dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+            hb.hydro_rk3_step(grid, U, W1, W2, Un, 0.4, dt)
+            torch.cuda.synchronize()
+            assert hb.hydro_check_status(grid) == hb.HYDRO_OK
+            outs.append(Un.cpu().numpy())
+    finally:
+        hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_3D_WORKGROUP, old)
+    assert np.array_equal(outs[0], outs[1])
+    if dtype == 0:
+        oracle.set_omega(0.7)
+        ref, _, _ = oracle.rk3_step(T, w.U, 0.4, reflux=True)
+        err = _rel(outs[0], ref)
+        print(f"  rel err {err.max():.3e} bit-exact {np.array_equal(outs[0], ref)}")
+        assert np.all(err <= TOL64), err
