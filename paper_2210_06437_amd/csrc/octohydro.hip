@@ -368,7 +368,8 @@ __global__ void __launch_bounds__(256) k_fill(GridArgs g, const T* __restrict__ 
       for (int f = 0; f < g.nf; ++f)
         Gl[f * fsG + t] = neighbour_value<T>(g, U + f * fsU, leaf, ic, blocks, kind, id, r, l);
     } else {
-      // a copy: the cell itself, a same-level cell or the covering coarse cell
+      // a copy: the cell itself, a same-level cell or the covering coarse
+      // cell; every field's load is issued before the first store
       const T* __restrict__ src = U;
       size_t o;
       if (kind == HYDRO_SAME_LEAF) {
@@ -382,7 +383,13 @@ __global__ void __launch_bounds__(256) k_fill(GridArgs g, const T* __restrict__ 
         }
         o = (size_t)id * CELLS + c[2] * 64 + c[1] * 8 + c[0];
       }
-      for (int f = 0; f < g.nf; ++f) Gl[f * fsG + t] = src[f * fsU + o];
+      T v[16];
+#pragma unroll
+      for (int f = 0; f < 16; ++f)
+        if (f < g.nf) v[f] = src[f * fsU + o];
+#pragma unroll
+      for (int f = 0; f < 16; ++f)
+        if (f < g.nf) Gl[f * fsG + t] = v[f];
     }
   }
 }
