@@ -480,8 +480,9 @@ def main():
         ops3 = ops_per_leaf_stage_3d(nf, True) * n
         recon3d = {"value": cells / (ms3 * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms3,
                    "steps": steps3,
-                   "kernel": "k_step3d_wg<double,11> (3D reconstruction, 9-point Simpson flux, "
-                             "one workgroup per leaf)",
+                   "kernel": "k_step3d_ws<double,11> (3D reconstruction, 9-point Simpson flux, "
+                             "one workgroup per leaf, each (cell, line) reconstructed once "
+                             "per face orientation)",
                    "kernel_ms": kms3, "ghost_fill_ms": fill3, "ops_per_launch": ops3,
                    "alu_frac": ops3 / (kms3 * 1e-3) / ALU_PEAK,
                    "hbm_frac": hbm_bytes_per_leaf_stage(nf, 8, True) * n / (kms3 * 1e-3) / HBM_PEAK}

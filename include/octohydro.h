@@ -362,10 +362,15 @@ const char* hydro_last_error(void);
  *                             node_state2_dev lets its substeps leave the
  *                             node copies of their outputs (1) or makes
  *                             them in a pass before each substep (0)
- *   HYDRO_OPT_3D_WORKGROUP    1 or 0: the 3D step with one 256-thread
- *                             workgroup per leaf (where its face fluxes fit
- *                             in LDS: binary64 up to 11 fields, binary32 up
- *                             to 16) or one wavefront per leaf
+ *   HYDRO_OPT_3D_WORKGROUP    0, 1 or 2: the 3D step with one wavefront
+ *                             per leaf (0) or one 256-thread workgroup per
+ *                             leaf where its face fluxes fit in LDS
+ *                             (binary64 up to 11 fields, binary32 up to
+ *                             16): evaluating each face from both sides'
+ *                             line parabolas (1), or reconstructing each
+ *                             (cell, line) once per face orientation and
+ *                             using both ends of its parabola (2, the
+ *                             default)
  * Every choice computes the same bits.  Options are process-wide and take effect at the next launch (a captured
  * graph keeps the kernel it was captured with).  Host only, thread-safe.
  */

@@ -1,12 +1,13 @@
 // liboctohydro: octree hydro step for gfx950 (AMD Instinct MI355X).  This
 // unit holds the C-ABI entry points, the host-side launch logic and the
 // small kernels; the method's device code and the step kernels are in
-// octohydro_kernels.h, instantiated in k_step_f64.hip, k_step_f32.hip and
-// k_step3d.hip.
+// octohydro_kernels.h (the 3D step's in octohydro_kernels3d.h), instantiated
+// in the k_step_*.hip and k_step3d*.hip units.
 //
 // Kernels behind the C-ABI in include/octohydro.h:
 //   k_fill     ghost fill into materialised 14^3 tiles (hydro_fill_ghosts)
 //   k_restrict restricted copies of the refined nodes, before a substep
+//              (within an RK3 step the substeps leave them after the first)
 //   k_step     fused substep: neighbour gather + PPM + Kurganov-Tadmor flux +
 //              flux divergence + Runge-Kutta stage combination (hydro_step)
 //   k_step3d   the same with the full 3D reconstruction and face quadrature
@@ -431,7 +432,7 @@ struct Options {
   int waves_per_leaf = 1;
   int cfl_epilogue = 1;
   int fused_restrict = 1;
-  int recon3d_wg = 1;
+  int recon3d_wg = 2;
 };
 static Options g_opts[2][17];
 static std::mutex g_opts_mu;
@@ -717,8 +718,8 @@ int hydro_set_option(int32_t dtype, int32_t n_fields, int32_t option, int32_t va
       o.xcd_remap = value;
       return HYDRO_OK;
     case HYDRO_OPT_3D_WORKGROUP:
-      if (value != 0 && value != 1)
-        return fail(HYDRO_E_ARG, "hydro_set_option: 3D workgroup form is 0 or 1");
+      if (value < 0 || value > 2)
+        return fail(HYDRO_E_ARG, "hydro_set_option: 3D workgroup form is 0, 1 or 2");
       o.recon3d_wg = value;
       return HYDRO_OK;
     case HYDRO_OPT_FUSED_RESTRICT:
@@ -952,9 +953,12 @@ int hydro_graph_destroy(void* graph) {
   clear_error();
   if (!graph) return HYDRO_OK;
   Graph* h = static_cast<Graph*>(graph);
-  if (h->exec) HIP_TRY(hipGraphExecDestroy(h->exec));
-  if (h->graph) HIP_TRY(hipGraphDestroy(h->graph));
+  // both are released and the handle freed whatever either call returns
+  const hipError_t e1 = h->exec ? hipGraphExecDestroy(h->exec) : hipSuccess;
+  const hipError_t e2 = h->graph ? hipGraphDestroy(h->graph) : hipSuccess;
   delete h;
+  const hipError_t e = e1 != hipSuccess ? e1 : e2;
+  if (e != hipSuccess) return fail(HYDRO_E_HIP, "hydro_graph_destroy: %s", hipGetErrorString(e));
   return HYDRO_OK;
 }
 

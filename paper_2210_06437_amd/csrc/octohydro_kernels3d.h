@@ -29,16 +29,28 @@ namespace octohydro {
 // diagonal lines reach edge and corner ghosts).
 // ---------------------------------------------------------------------------
 
-// One end of the PPM parabola of the cell at t along a line of tile stride s.
+// The PPM parabola of the cell at t along a line of tile stride s: its ends
+// at t - s/2 (l) and t + s/2 (r).  Walking the line the other way (stride
+// -s) gives the same two values with l and r exchanged, bit for bit: the
+// limited slopes change sign exactly (or stay +0), the interface values and
+// the monotonisation are symmetric in the two ends, and every sum involved
+// is commutative.
 template <typename T>
-__device__ __forceinline__ T line_end(const T* __restrict__ t, int s, bool right) {
+__device__ __forceinline__ void parabola(const T* __restrict__ t, int s, T& l, T& r) {
   const T q0 = t[-2 * s], q1 = t[-s], q2 = t[0], q3 = t[s], q4 = t[2 * s];
   const T dm1 = limited_slope(q0, q1, q2);
   const T dm2 = limited_slope(q1, q2, q3);
   const T dm3 = limited_slope(q2, q3, q4);
-  T l = T(0.5) * (q1 + q2) - (dm2 - dm1) * T(1.0 / 6.0);
-  T r = T(0.5) * (q2 + q3) - (dm3 - dm2) * T(1.0 / 6.0);
+  l = T(0.5) * (q1 + q2) - (dm2 - dm1) * T(1.0 / 6.0);
+  r = T(0.5) * (q2 + q3) - (dm3 - dm2) * T(1.0 / 6.0);
   monotonise(q2, l, r);
+}
+
+// One end of the PPM parabola of the cell at t along a line of tile stride s.
+template <typename T>
+__device__ __forceinline__ T line_end(const T* __restrict__ t, int s, bool right) {
+  T l, r;
+  parabola(t, s, l, r);
   return right ? r : l;
 }
 
@@ -393,6 +405,53 @@ constexpr size_t wg3d_lds_bytes() {
   return (size_t)FACE_PLANES * 64 * NF * sizeof(T);
 }
 
+// Cell finishing of the workgroup forms, after the barrier that follows the
+// face fluxes: thread t of the 256 takes cells t and t + 256, each with the
+// binary64 sums ((xhi - xlo) + (yhi - ylo)) + (zhi - zlo) from the flux
+// store Hs (the layout of k_step3d_wg).
+template <typename T, int NF, int P>
+__device__ __forceinline__ void finish_leaf_3d(const StepArgs& s, const T (&Hs)[P][NF][64],
+                                               int leaf, int4 c4) {
+  const GridArgs& g = s.g;
+  const int blocks = g.base << c4.x;
+  const double dt = *s.dt;
+  const double inv_dx = (double)(SUB * blocks);
+  const double dx = 1.0 / (double)(SUB * blocks);
+  const size_t fs = (size_t)g.n_leaves * CELLS;
+  const T* __restrict__ Uk = static_cast<const T*>(s.Uk);
+  const T* __restrict__ U0 = static_cast<const T*>(s.U0);
+#pragma unroll 1
+  for (int c = threadIdx.x; c < CELLS; c += 256) {
+    const int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
+    const int xy = y * 8 + x;
+    const uint32_t at = (uint32_t)leaf * CELLS + c;
+    double src[4] = {0.0, 0.0, 0.0, 0.0};
+    const bool rot = g.omega != 0.0;
+    if (rot) {
+      const double rx = ((double)(SUB * c4.y + x) + 0.5) * dx - 0.5;
+      const double ry = ((double)(SUB * c4.z + y) + 0.5) * dx - 0.5;
+      const double rho = (double)Uk[at], sx = (double)Uk[fs + at], sy = (double)Uk[2 * fs + at];
+      const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
+      src[0] = tw * sy + rho * om2 * rx;
+      src[1] = rho * om2 * ry - tw * sx;
+      src[3] = om2 * (sx * rx + sy * ry);
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double xlo = (double)Hs[z][f][xy];
+      const double xhi = (double)(x == SUB - 1 ? Hs[SUB][f][z * 8 + y] : Hs[z][f][xy + 1]);
+      const double ylo = (double)Hs[9 + z][f][xy];
+      const double yhi = (double)(y == SUB - 1 ? Hs[9 + SUB][f][z * 8 + x] : Hs[9 + z][f][xy + 8]);
+      const double zlo = (double)Hs[18 + z][f][xy];
+      const double zhi = (double)Hs[18 + z + 1][f][xy];
+      const double sum = ((xhi - xlo) + (yhi - ylo)) + (zhi - zlo);
+      const T u0 = U0 ? U0[(size_t)f * fs + at] : T(0);
+      finish_cell<T>(s, (size_t)f * fs, at, Uk[(size_t)f * fs + at], u0, sum,
+                     rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+    }
+  }
+}
+
 template <typename T, int NF>
 __global__ void __launch_bounds__(256, 1) k_step3d_wg(StepArgs s, const T* __restrict__ G) {
   // fluxes, [plane][field][lane]: planes 0-7 low x-faces, 8 high x-faces,
@@ -404,7 +463,6 @@ __global__ void __launch_bounds__(256, 1) k_step3d_wg(StepArgs s, const T* __res
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
-  const int blocks = g.base << c4.x;
   Phys<T> ph;
   ph.gamma = (T)g.gamma;
   ph.gm1 = (T)(g.gamma - 1.0);
@@ -450,54 +508,392 @@ __global__ void __launch_bounds__(256, 1) k_step3d_wg(StepArgs s, const T* __res
   }
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
   __syncthreads();
+  finish_leaf_3d<T, NF, FACE_PLANES>(s, Hs, leaf, c4);
+}
 
-  // finish the leaf's cells: thread t takes cells t and t + 256
-  const double dt = *s.dt;
-  const double inv_dx = (double)(SUB * blocks);
-  const double dx = 1.0 / (double)(SUB * blocks);
-  const size_t fs = (size_t)g.n_leaves * CELLS;
-  const T* __restrict__ Uk = static_cast<const T*>(s.Uk);
-  const T* __restrict__ U0 = static_cast<const T*>(s.U0);
-#pragma unroll 1
-  for (int c = threadIdx.x; c < CELLS; c += 256) {
-    const int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
-    const int xy = y * 8 + x;
-    const uint32_t at = (uint32_t)leaf * CELLS + c;
-    double src[4] = {0.0, 0.0, 0.0, 0.0};
-    const bool rot = g.omega != 0.0;
-    if (rot) {
-      const double rx = ((double)(SUB * c4.y + x) + 0.5) * dx - 0.5;
-      const double ry = ((double)(SUB * c4.z + y) + 0.5) * dx - 0.5;
-      const double rho = (double)Uk[at], sx = (double)Uk[fs + at], sy = (double)Uk[2 * fs + at];
-      const double om2 = g.omega * g.omega, tw = 2.0 * g.omega;
-      src[0] = tw * sy + rho * om2 * rx;
-      src[1] = rho * om2 * ry - tw * sx;
-      src[3] = om2 * (sx * rx + sy * ry);
+// ---------------------------------------------------------------------------
+// The 3D step with shared line reconstructions (launch option value 2): the
+// workgroup, flux store and cell finishing of k_step3d_wg, with face fluxes
+// from tasks that reconstruct each (cell, line) once per face orientation
+// and use both ends of its parabola.
+//  - Plane task (D, z), D = x or y: lane (x, y) holds cell (x, y, z).  The
+//    faces normal to D use the 9 lines e(a, b) = D + a u + b v, where u < v
+//    are the face's transverse axes and a, b are in {-1, 0, 1}.  Face c - 1/2
+//    along D takes at point (a, b) the right end of e(a, b) of the cell
+//    below it (the lane before along D: a DPP shift of one lane for x, a
+//    shuffle of 8 lanes for y) as its left state, and the left end of
+//    e(-a, -b) of its own cell as its right state.  Each lane with c >= 1
+//    gets one face; faces 0 and 8 come from the boundary tasks.
+//  - Boundary task: face 0 or face 8 along x or y for the whole leaf, one
+//    face per lane, evaluated as in k_step3d_wg (both sides' line ends).
+//  - Column task: lane (x, y) walks up its column, carrying the right ends
+//    of the 9 lines a x + b y + z of the cell below; face c - 1/2 takes the
+//    carried end of e(a, b) and the left end of e(-a, -b) of cell c at point
+//    (a, b).  Two tasks split the column: faces 0..3 and 4..8.
+// The lines are walked in the direction of the face normal, not always in
+// the canonical direction of the point, and parabola() gives the same ends
+// either way.  The points are taken in pairs (a, b) and (-a, -b), whose two
+// lines give both points' states, in the order of the Simpson sums, so each
+// face's flux is the sequence of operations face_flux_3d performs: the same
+// bits.
+// ---------------------------------------------------------------------------
+
+// The flux store of k_step3d_ws: k_step3d_wg's 27 planes and a spare one
+// that takes the stores of lanes without a face, so that every store is
+// unconditional (a conditional one lets the compiler sink the flux
+// arithmetic behind it, away from the lane moves it depends on, which then
+// hold their registers to the end of the task).
+constexpr int WS_PLANES = FACE_PLANES + 1;
+constexpr int WS_SPARE = FACE_PLANES;
+template <typename T, int NF>
+constexpr size_t ws3d_lds_bytes() {
+  return (size_t)WS_PLANES * 64 * NF * sizeof(T);
+}
+
+// Point pairs (a, b), (-a, -b) in the order of the Simpson sums; the last is
+// the centre point, a line of its own.
+constexpr int WS_PA[5] = {1, 1, 0, 1, 0};
+constexpr int WS_PB[5] = {1, -1, 1, 0, 0};
+
+// Running Simpson sums of one field over the pairs: pair 0 gives
+// (h(-1,-1) + h(1,1)), pair 1 adds (h(1,-1) + h(-1,1)) for the corners,
+// pairs 2 and 3 do the same for the edges, the centre closes the sum.
+template <typename T>
+__device__ __forceinline__ void simpson_pair(int p, T hp, T hm, T& sa, T& sb, T& out) {
+  if (p == 0) sa = hm + hp;
+  else if (p == 1) sa = sa + (hp + hm);
+  else if (p == 2) sb = hm + hp;
+  else if (p == 3) sb = sb + (hm + hp);
+  else out = ((sa + T(4) * sb) + T(16) * hp) / T(36);
+}
+
+// Value of the previous cell along D within the lane's cell plane, lane
+// (x, y) = x + 8 y: for x, lane - 1 by a DPP row shift (the lanes without a
+// source keep the value itself, so no register has to be cleared for them);
+// for y, lane - 8 by a shuffle.  Lanes at the plane's first cell along D
+// receive a value they never use.  (Lanes ordered (y, x), which would let y
+// use the DPP shift too, measured no faster.)
+__device__ __forceinline__ int row_shr1(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+}
+template <int D, typename T>
+__device__ __forceinline__ T prev_cell(T v) {
+  if constexpr (D == 0) {
+    if constexpr (sizeof(T) == 8) {
+      const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+      const int lo = row_shr1((int)(unsigned)b), hi = row_shr1((int)(unsigned)(b >> 32));
+      return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                              (unsigned long long)(unsigned)lo));
+    } else {
+      return __int_as_float(row_shr1(__float_as_int(v)));
     }
+  } else {
+    return __shfl_up(v, 8, 64);
+  }
+}
+
+// Keeps a value's computation ahead of this point in program order.  The
+// instruction selector otherwise orders pure arithmetic its own way: it
+// computed a pair's parabola ends early and their monotonisation late, so
+// they held registers to the end of the task (the plane task at 11 binary64
+// fields spilled 248 VGPRs; with the pins it takes 300 and spills none).
+// An empty statement on a register: no instruction, no memory access.
+template <typename T>
+__device__ __forceinline__ void ws_pin(T& v) {
+  asm volatile("" : "+v"(v));
+}
+
+// Kurganov-Tadmor flux of one passive field at a point from the point's
+// velocities and half signal speed.
+template <typename T>
+__device__ __forceinline__ T passive_flux(T ul, T ur, T vl, T vr, T ha) {
+  return T(0.5) * (ul * vl + ur * vr) - ha * (ur - ul);
+}
+
+// Plane task: faces 1..7 along D (0: x, 1: y) of cell plane z into Hs.
+// The core fields go first over all point pairs and leave each point's
+// velocities and half signal speed (point slot 2p: (a, b), 2p + 1:
+// (-a, -b), 8: the centre); each species then goes over the pairs on its
+// own, so only one species' line ends are held at a time.
+template <typename T, int NF, int D>
+__device__ __forceinline__ void ws_plane(const Phys<T>& ph, const T* __restrict__ Gt, size_t fsG,
+                                         int z, int lane, T (&Hs)[WS_PLANES][NF][64],
+                                         bool& bad) {
+  constexpr int SD = D == 0 ? 1 : TW;       // tile stride along D
+  constexpr int SU = D == 0 ? TW : 1;       // along u (y for x-faces, x for y-faces)
+  constexpr int SV = TW * TW;               // along v (z)
+  const int x = lane & 7, y = lane >> 3;
+  const int t = tile_at(x, y, z);
+  T sa[NF_CORE], sb[NF_CORE], H[NF];
+  T vl[9], vr[9], ha[9];
+  bool b2 = false;
+#pragma unroll
+  for (int p = 0; p < 5; ++p) {
+    const int sA = SD + WS_PA[p] * SU + WS_PB[p] * SV;  // line e(a, b)
+    const int sB = SD - WS_PA[p] * SU - WS_PB[p] * SV;  // line e(-a, -b)
+    T ULp[NF_CORE], URp[NF_CORE], ULm[NF_CORE], URm[NF_CORE];
+#pragma unroll
+    for (int f = 0; f < NF_CORE; ++f) {
+      T lA, rA;
+      parabola(Gt + f * fsG + t, sA, lA, rA);
+      ULp[f] = prev_cell<D>(rA);
+      if (p < 4) {
+        T lB, rB;
+        parabola(Gt + f * fsG + t, sB, lB, rB);
+        URp[f] = lB;
+        ULm[f] = prev_cell<D>(rB);
+        URm[f] = lA;
+      } else {
+        URp[f] = lA;
+      }
+    }
+    T Hp[NF_CORE], Hm[NF_CORE];
+    core_flux(ph, D, ULp, URp, Hp, vl[2 * p], vr[2 * p], ha[2 * p], b2);
+    if (p < 4) core_flux(ph, D, ULm, URm, Hm, vl[2 * p + 1], vr[2 * p + 1], ha[2 * p + 1], b2);
+#pragma unroll
+    for (int f = 0; f < NF_CORE; ++f) {
+      simpson_pair(p, Hp[f], p < 4 ? Hm[f] : T(0), sa[f], sb[f], H[f]);
+      ws_pin(p < 2 ? sa[f] : (p < 4 ? sb[f] : H[f]));
+    }
+    ws_pin(vl[2 * p]);
+    ws_pin(vr[2 * p]);
+    ws_pin(ha[2 * p]);
+    if (p < 4) {
+      ws_pin(vl[2 * p + 1]);
+      ws_pin(vr[2 * p + 1]);
+      ws_pin(ha[2 * p + 1]);
+    }
+  }
+#pragma unroll
+  for (int f = NF_CORE; f < NF; ++f) {
+    T fa = T(0), fb = T(0);
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      const int sA = SD + WS_PA[p] * SU + WS_PB[p] * SV;
+      const int sB = SD - WS_PA[p] * SU - WS_PB[p] * SV;
+      T lA, rA, hp, hm = T(0);
+      parabola(Gt + f * fsG + t, sA, lA, rA);
+      if (p < 4) {
+        T lB, rB;
+        parabola(Gt + f * fsG + t, sB, lB, rB);
+        hp = passive_flux(prev_cell<D>(rA), lB, vl[2 * p], vr[2 * p], ha[2 * p]);
+        hm = passive_flux(prev_cell<D>(rB), lA, vl[2 * p + 1], vr[2 * p + 1], ha[2 * p + 1]);
+      } else {
+        hp = passive_flux(prev_cell<D>(rA), lA, vl[2 * p], vr[2 * p], ha[2 * p]);
+      }
+      simpson_pair(p, hp, hm, fa, fb, H[f]);
+      ws_pin(p < 2 ? fa : (p < 4 ? fb : H[f]));
+    }
+  }
+  const bool has_face = (D == 0 ? x : y) != 0;
+  bad |= b2 && has_face;
+  const int slot = has_face ? (D == 0 ? 0 : 9) + z : WS_SPARE;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) Hs[slot][f][lane] = H[f];
+}
+
+// Boundary task k (0: x-face 0, 1: x-face 8, 2: y-face 0, 3: y-face 8):
+// lane (a, b) is the face's transverse position ((y, z) or (x, z)).
+template <typename T, int NF>
+__device__ __forceinline__ void ws_boundary(const GridArgs& g, const Phys<T>& ph,
+                                            const T* __restrict__ Gt, size_t fsG, int leaf,
+                                            int k, int lane, T (&Hs)[WS_PLANES][NF][64],
+                                            bool& bad) {
+  const int a = lane & 7, b = lane >> 3;
+  const bool hi = (k & 1) != 0;
+  T H[NF];
+  if (k < 2) {
+    face_flux_3d<T, NF, 0>(ph, Gt, fsG, hi ? tile_at(SUB - 1, a, b) : tile_at(-1, a, b), H, bad);
+    if (g.reg) record_face<T, NF>(g, face_slots_3d(g, leaf, 0), hi ? SUB : 0, a, b, H);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      const double xlo = (double)Hs[z][f][xy];
-      const double xhi = (double)(x == SUB - 1 ? Hs[SUB][f][z * 8 + y] : Hs[z][f][xy + 1]);
-      const double ylo = (double)Hs[9 + z][f][xy];
-      const double yhi = (double)(y == SUB - 1 ? Hs[9 + SUB][f][z * 8 + x] : Hs[9 + z][f][xy + 8]);
-      const double zlo = (double)Hs[18 + z][f][xy];
-      const double zhi = (double)Hs[18 + z + 1][f][xy];
-      const double sum = ((xhi - xlo) + (yhi - ylo)) + (zhi - zlo);
-      const T u0 = U0 ? U0[(size_t)f * fs + at] : T(0);
-      finish_cell<T>(s, (size_t)f * fs, at, Uk[(size_t)f * fs + at], u0, sum,
-                     rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0, dt, inv_dx);
+      if (hi) Hs[SUB][f][lane] = H[f];
+      else Hs[b][f][8 * a] = H[f];  // face 0 of row (y, z) = (a, b)
+    }
+  } else {
+    face_flux_3d<T, NF, 1>(ph, Gt, fsG, hi ? tile_at(a, SUB - 1, b) : tile_at(a, -1, b), H, bad);
+    if (g.reg) record_face<T, NF>(g, face_slots_3d(g, leaf, 1), hi ? SUB : 0, a, b, H);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      if (hi) Hs[9 + SUB][f][lane] = H[f];
+      else Hs[9 + b][f][a] = H[f];  // face 0 of column (x, z) = (a, b)
     }
   }
 }
 
-// Launch of the 3D step: the workgroup-per-leaf form where its flux store
-// fits in LDS (binary64 up to 11 fields, binary32 up to 16) unless the
-// one-wavefront form is asked for (wg == 0), else k_step3d.
+// Column task: z-faces c0..c1 of lane (x, y)'s column into Hs, in the
+// field order of the plane task.  The cell below face c0 only fills the
+// carry.
+template <typename T, int NF>
+__device__ __forceinline__ void ws_column(const GridArgs& g, const Phys<T>& ph,
+                                          const T* __restrict__ Gt, size_t fsG, int leaf, int c0,
+                                          int c1, int lane, T (&Hs)[WS_PLANES][NF][64],
+                                          bool& bad) {
+  constexpr int SU = 1, SV = TW, SD = TW * TW;
+  const int x = lane & 7, y = lane >> 3;
+  // right ends of the cell below: [2p] line e(a, b), [2p + 1] line e(-a, -b)
+  T cr[9][NF];
+  {
+    const int t = tile_at(x, y, c0 - 1);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+      for (int p = 0; p < 5; ++p) {
+        T l;
+        parabola(Gt + f * fsG + t, SD + WS_PA[p] * SU + WS_PB[p] * SV, l, cr[2 * p][f]);
+        ws_pin(cr[2 * p][f]);
+        if (p < 4) {
+          parabola(Gt + f * fsG + t, SD - WS_PA[p] * SU - WS_PB[p] * SV, l, cr[2 * p + 1][f]);
+          ws_pin(cr[2 * p + 1][f]);
+        }
+      }
+    }
+  }
+#pragma unroll 1
+  for (int c = c0; c <= c1; ++c) {
+    const int t = tile_at(x, y, c);
+    T sa[NF_CORE], sb[NF_CORE], H[NF];
+    T vl[9], vr[9], ha[9];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      const int sA = SD + WS_PA[p] * SU + WS_PB[p] * SV;
+      const int sB = SD - WS_PA[p] * SU - WS_PB[p] * SV;
+      T ULp[NF_CORE], URp[NF_CORE], ULm[NF_CORE], URm[NF_CORE];
+#pragma unroll
+      for (int f = 0; f < NF_CORE; ++f) {
+        T lA, rA;
+        parabola(Gt + f * fsG + t, sA, lA, rA);
+        ULp[f] = cr[2 * p][f];
+        cr[2 * p][f] = rA;
+        if (p < 4) {
+          T lB, rB;
+          parabola(Gt + f * fsG + t, sB, lB, rB);
+          URp[f] = lB;
+          ULm[f] = cr[2 * p + 1][f];
+          cr[2 * p + 1][f] = rB;
+          URm[f] = lA;
+        } else {
+          URp[f] = lA;
+        }
+      }
+      T Hp[NF_CORE], Hm[NF_CORE];
+      core_flux(ph, 2, ULp, URp, Hp, vl[2 * p], vr[2 * p], ha[2 * p], bad);
+      if (p < 4)
+        core_flux(ph, 2, ULm, URm, Hm, vl[2 * p + 1], vr[2 * p + 1], ha[2 * p + 1], bad);
+#pragma unroll
+      for (int f = 0; f < NF_CORE; ++f) {
+        simpson_pair(p, Hp[f], p < 4 ? Hm[f] : T(0), sa[f], sb[f], H[f]);
+        ws_pin(p < 2 ? sa[f] : (p < 4 ? sb[f] : H[f]));
+      }
+      ws_pin(vl[2 * p]);
+      ws_pin(vr[2 * p]);
+      ws_pin(ha[2 * p]);
+      if (p < 4) {
+        ws_pin(vl[2 * p + 1]);
+        ws_pin(vr[2 * p + 1]);
+        ws_pin(ha[2 * p + 1]);
+      }
+#pragma unroll
+      for (int f = 0; f < NF_CORE; ++f) {
+        ws_pin(cr[2 * p][f]);
+        if (p < 4) ws_pin(cr[2 * p + 1][f]);
+      }
+    }
+#pragma unroll
+    for (int f = NF_CORE; f < NF; ++f) {
+      T fa = T(0), fb = T(0);
+#pragma unroll
+      for (int p = 0; p < 5; ++p) {
+        const int sA = SD + WS_PA[p] * SU + WS_PB[p] * SV;
+        const int sB = SD - WS_PA[p] * SU - WS_PB[p] * SV;
+        T lA, rA, hp, hm = T(0);
+        parabola(Gt + f * fsG + t, sA, lA, rA);
+        const T ulp = cr[2 * p][f];
+        cr[2 * p][f] = rA;
+        if (p < 4) {
+          T lB, rB;
+          parabola(Gt + f * fsG + t, sB, lB, rB);
+          const T ulm = cr[2 * p + 1][f];
+          cr[2 * p + 1][f] = rB;
+          hp = passive_flux(ulp, lB, vl[2 * p], vr[2 * p], ha[2 * p]);
+          hm = passive_flux(ulm, lA, vl[2 * p + 1], vr[2 * p + 1], ha[2 * p + 1]);
+        } else {
+          hp = passive_flux(ulp, lA, vl[2 * p], vr[2 * p], ha[2 * p]);
+        }
+        simpson_pair(p, hp, hm, fa, fb, H[f]);
+        ws_pin(p < 2 ? fa : (p < 4 ? fb : H[f]));
+        ws_pin(cr[2 * p][f]);
+        if (p < 4) ws_pin(cr[2 * p + 1][f]);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) Hs[18 + c][f][lane] = H[f];
+    if (g.reg && (c == 0 || c == SUB))
+      record_face<T, NF>(g, face_slots_3d(g, leaf, 2), c, x, y, H);
+  }
+}
+
+// Work of each wavefront (measured in clocks, the four finish their tasks
+// within 8 % of each other at 11 binary64 fields; a plane task is about an
+// eighth of a wavefront's work, so no other split does better):
+//   0: z-faces 4..8, y-face 8, y-face plane 7
+//   1: z-faces 0..3, x-face 0, y-face planes 5, 6
+//   2: x-face 8, y-face 0, y-face planes 0..4
+//   3: x-face planes 0..7
+// written out per wavefront, not as a list of tasks in one loop: in a loop
+// the compiler keeps every task's loop-invariant values in registers
+// through all of them.
+// binary32 at two workgroups per CU (256 registers; its flux store is 77 KB
+// at 11 fields), binary64 at one.
+template <typename T, int NF>
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
+    k_step3d_ws(StepArgs s, const T* __restrict__ G) {
+  __shared__ T Hs[WS_PLANES][NF][64];  // the layout of k_step3d_wg and a spare plane
+  const GridArgs& g = s.g;
+  const int leaf = s.leaf_base + blockIdx.x;
+  if (leaf >= g.n_leaves) return;  // uniform over the workgroup
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
+  Phys<T> ph;
+  ph.gamma = (T)g.gamma;
+  ph.gm1 = (T)(g.gamma - 1.0);
+  ph.eta1 = (T)g.eta1;
+  const size_t fsG = (size_t)g.n_leaves * TILE;
+  const T* __restrict__ Gt = G + (size_t)leaf * TILE;
+  bool bad = false;
+  if (wave == 3) {
+#pragma unroll 1
+    for (int z = 0; z < SUB; ++z) ws_plane<T, NF, 0>(ph, Gt, fsG, z, lane, Hs, bad);
+  } else {
+    if (wave < 2)
+      ws_column<T, NF>(g, ph, Gt, fsG, leaf, wave == 0 ? 4 : 0, wave == 0 ? SUB : 3, lane, Hs, bad);
+    const int k0 = wave == 0 ? 3 : (wave == 1 ? 0 : 1), k1 = wave == 2 ? 2 : k0;
+#pragma unroll 1
+    for (int k = k0; k <= k1; ++k) ws_boundary<T, NF>(g, ph, Gt, fsG, leaf, k, lane, Hs, bad);
+    const int z0 = wave == 0 ? 7 : (wave == 1 ? 5 : 0), z1 = wave == 0 ? 7 : (wave == 1 ? 6 : 4);
+#pragma unroll 1
+    for (int z = z0; z <= z1; ++z) ws_plane<T, NF, 1>(ph, Gt, fsG, z, lane, Hs, bad);
+  }
+  if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
+  __syncthreads();
+  finish_leaf_3d<T, NF, WS_PLANES>(s, Hs, leaf, c4);
+}
+
+// Launch of the 3D step: where the workgroup forms' flux store fits in LDS
+// (binary64 up to 11 fields, binary32 up to 16), the form wg asks for (1:
+// k_step3d_wg, 2: k_step3d_ws); else, or for wg == 0, k_step3d.
 template <typename T, int NF>
 hipError_t launch_step3d_one(const StepArgs& a, int blocks, const T* G, int wg, hipStream_t st) {
   if constexpr (wg3d_lds_bytes<T, NF>() <= 160 * 1024) {
-    if (wg) {
+    if (wg == 1) {
       hipLaunchKernelGGL((k_step3d_wg<T, NF>), dim3(blocks), dim3(256), 0, st, a, G);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (ws3d_lds_bytes<T, NF>() <= 160 * 1024) {
+    if (wg == 2) {
+      hipLaunchKernelGGL((k_step3d_ws<T, NF>), dim3(blocks), dim3(256), 0, st, a, G);
       return hipGetLastError();
     }
   }

@@ -152,6 +152,11 @@ def test_launch_options_roundtrip_and_validation(hb):
         hb.hydro_set_option(1, 11, hb.HYDRO_OPT_CFL_EPILOGUE, epi)
         assert hb.hydro_get_option(1, 11, hb.HYDRO_OPT_CFL_EPILOGUE) == epi
         hb.hydro_set_option(1, 11, hb.HYDRO_OPT_CFL_EPILOGUE, e0)
+    for form in (0, 1, 2):
+        f0 = hb.hydro_get_option(0, 11, hb.HYDRO_OPT_3D_WORKGROUP)
+        hb.hydro_set_option(0, 11, hb.HYDRO_OPT_3D_WORKGROUP, form)
+        assert hb.hydro_get_option(0, 11, hb.HYDRO_OPT_3D_WORKGROUP) == form
+        hb.hydro_set_option(0, 11, hb.HYDRO_OPT_3D_WORKGROUP, f0)
     for remap in (0, 1, 2, 64, 4096):
         r0 = hb.hydro_get_option(0, 11, hb.HYDRO_OPT_XCD_REMAP)
         hb.hydro_set_option(0, 11, hb.HYDRO_OPT_XCD_REMAP, remap)
@@ -161,7 +166,7 @@ def test_launch_options_roundtrip_and_validation(hb):
     # or a power of two up to 4096
     for bad in ((0, 6, 1, 3), (0, 5, 1, 1), (2, 6, 1, 1), (0, 6, 9, 1), (1, 17, 2, 1),
                 (0, 6, 2, 5), (0, 6, 2, -1), (0, 6, 2, 8192), (0, 6, 3, 2), (1, 11, 3, 3),
-                (0, 11, 3, 0), (0, 11, 4, 2), (0, 11, 5, 3), (1, 11, 6, 2)):
+                (0, 11, 3, 0), (0, 11, 4, 2), (0, 11, 5, 3), (1, 11, 6, 3), (0, 6, 6, -1)):
         with pytest.raises(hb.HydroError) as e:
             hb.hydro_set_option(*bad)
         assert e.value.code == hb.HYDRO_E_ARG

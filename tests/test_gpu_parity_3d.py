@@ -203,8 +203,10 @@ def test_sampled_leaves_of_the_turbulence_workload_3d(env, recon3d):
 
 @pytest.mark.parametrize("dtype,nf", [(0, 11), (0, 6), (0, 14), (1, 11), (1, 16)])
 def test_workgroup_and_wavefront_forms_give_the_same_bits(env, recon3d, dtype, nf):
-    """The 3D step with one workgroup per leaf (face fluxes in LDS) and with
-    one wavefront per leaf: the same bits, with the flux correction and the
+    """The 3D step in its three forms -- one workgroup per leaf evaluating
+    each face from both sides' line parabolas, one workgroup per leaf
+    reconstructing each (cell, line) once per face orientation, one
+    wavefront per leaf: the same bits, with the flux correction and the
     rotating frame on (binary64 beyond 11 fields has only the wavefront
     form); binary64 also against the oracle."""
     torch, hb = env
@@ -217,7 +219,7 @@ def test_workgroup_and_wavefront_forms_give_the_same_bits(env, recon3d, dtype, n
     old = hb.hydro_get_option(dtype, nf, hb.HYDRO_OPT_3D_WORKGROUP)
     outs = []
     try:
-        for form in (1, 0):
+        for form in (1, 2, 0):
             hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_3D_WORKGROUP, form)
             W1, W2, Un = grid.empty_state(), grid.empty_state(), grid.empty_state()
             dt = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -228,6 +230,7 @@ def test_workgroup_and_wavefront_forms_give_the_same_bits(env, recon3d, dtype, n
     finally:
         hb.hydro_set_option(dtype, nf, hb.HYDRO_OPT_3D_WORKGROUP, old)
     assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
     if dtype == 0:
         oracle.set_omega(0.7)
         ref, _, _ = oracle.rk3_step(T, w.U, 0.4, reflux=True)
