@@ -535,7 +535,9 @@ __global__ void __launch_bounds__(256, 1) k_step3d_wg(StepArgs s, const T* __res
 // either way.  The points are taken in pairs (a, b) and (-a, -b), whose two
 // lines give both points' states, in the order of the Simpson sums, so each
 // face's flux is the sequence of operations face_flux_3d performs: the same
-// bits.
+// bits.  Each pair's results are kept in program order (keep_order): without
+// that the plane task at 11 binary64 fields spilled 248 VGPRs, with it it
+// takes 300 and spills none.
 // ---------------------------------------------------------------------------
 
 // The flux store of k_step3d_ws: k_step3d_wg's 27 planes and a spare one
@@ -592,17 +594,6 @@ __device__ __forceinline__ T prev_cell(T v) {
   }
 }
 
-// Keeps a value's computation ahead of this point in program order.  The
-// instruction selector otherwise orders pure arithmetic its own way: it
-// computed a pair's parabola ends early and their monotonisation late, so
-// they held registers to the end of the task (the plane task at 11 binary64
-// fields spilled 248 VGPRs; with the pins it takes 300 and spills none).
-// An empty statement on a register: no instruction, no memory access.
-template <typename T>
-__device__ __forceinline__ void ws_pin(T& v) {
-  asm volatile("" : "+v"(v));
-}
-
 // Kurganov-Tadmor flux of one passive field at a point from the point's
 // velocities and half signal speed.
 template <typename T>
@@ -653,15 +644,15 @@ __device__ __forceinline__ void ws_plane(const Phys<T>& ph, const T* __restrict_
 #pragma unroll
     for (int f = 0; f < NF_CORE; ++f) {
       simpson_pair(p, Hp[f], p < 4 ? Hm[f] : T(0), sa[f], sb[f], H[f]);
-      ws_pin(p < 2 ? sa[f] : (p < 4 ? sb[f] : H[f]));
+      keep_order(p < 2 ? sa[f] : (p < 4 ? sb[f] : H[f]));
     }
-    ws_pin(vl[2 * p]);
-    ws_pin(vr[2 * p]);
-    ws_pin(ha[2 * p]);
+    keep_order(vl[2 * p]);
+    keep_order(vr[2 * p]);
+    keep_order(ha[2 * p]);
     if (p < 4) {
-      ws_pin(vl[2 * p + 1]);
-      ws_pin(vr[2 * p + 1]);
-      ws_pin(ha[2 * p + 1]);
+      keep_order(vl[2 * p + 1]);
+      keep_order(vr[2 * p + 1]);
+      keep_order(ha[2 * p + 1]);
     }
   }
 #pragma unroll
@@ -682,7 +673,7 @@ __device__ __forceinline__ void ws_plane(const Phys<T>& ph, const T* __restrict_
         hp = passive_flux(prev_cell<D>(rA), lA, vl[2 * p], vr[2 * p], ha[2 * p]);
       }
       simpson_pair(p, hp, hm, fa, fb, H[f]);
-      ws_pin(p < 2 ? fa : (p < 4 ? fb : H[f]));
+      keep_order(p < 2 ? fa : (p < 4 ? fb : H[f]));
     }
   }
   const bool has_face = (D == 0 ? x : y) != 0;
@@ -741,10 +732,10 @@ __device__ __forceinline__ void ws_column(const GridArgs& g, const Phys<T>& ph,
       for (int p = 0; p < 5; ++p) {
         T l;
         parabola(Gt + f * fsG + t, SD + WS_PA[p] * SU + WS_PB[p] * SV, l, cr[2 * p][f]);
-        ws_pin(cr[2 * p][f]);
+        keep_order(cr[2 * p][f]);
         if (p < 4) {
           parabola(Gt + f * fsG + t, SD - WS_PA[p] * SU - WS_PB[p] * SV, l, cr[2 * p + 1][f]);
-          ws_pin(cr[2 * p + 1][f]);
+          keep_order(cr[2 * p + 1][f]);
         }
       }
     }
@@ -783,20 +774,20 @@ __device__ __forceinline__ void ws_column(const GridArgs& g, const Phys<T>& ph,
 #pragma unroll
       for (int f = 0; f < NF_CORE; ++f) {
         simpson_pair(p, Hp[f], p < 4 ? Hm[f] : T(0), sa[f], sb[f], H[f]);
-        ws_pin(p < 2 ? sa[f] : (p < 4 ? sb[f] : H[f]));
+        keep_order(p < 2 ? sa[f] : (p < 4 ? sb[f] : H[f]));
       }
-      ws_pin(vl[2 * p]);
-      ws_pin(vr[2 * p]);
-      ws_pin(ha[2 * p]);
+      keep_order(vl[2 * p]);
+      keep_order(vr[2 * p]);
+      keep_order(ha[2 * p]);
       if (p < 4) {
-        ws_pin(vl[2 * p + 1]);
-        ws_pin(vr[2 * p + 1]);
-        ws_pin(ha[2 * p + 1]);
+        keep_order(vl[2 * p + 1]);
+        keep_order(vr[2 * p + 1]);
+        keep_order(ha[2 * p + 1]);
       }
 #pragma unroll
       for (int f = 0; f < NF_CORE; ++f) {
-        ws_pin(cr[2 * p][f]);
-        if (p < 4) ws_pin(cr[2 * p + 1][f]);
+        keep_order(cr[2 * p][f]);
+        if (p < 4) keep_order(cr[2 * p + 1][f]);
       }
     }
 #pragma unroll
@@ -821,9 +812,9 @@ __device__ __forceinline__ void ws_column(const GridArgs& g, const Phys<T>& ph,
           hp = passive_flux(ulp, lA, vl[2 * p], vr[2 * p], ha[2 * p]);
         }
         simpson_pair(p, hp, hm, fa, fb, H[f]);
-        ws_pin(p < 2 ? fa : (p < 4 ? fb : H[f]));
-        ws_pin(cr[2 * p][f]);
-        if (p < 4) ws_pin(cr[2 * p + 1][f]);
+        keep_order(p < 2 ? fa : (p < 4 ? fb : H[f]));
+        keep_order(cr[2 * p][f]);
+        if (p < 4) keep_order(cr[2 * p + 1][f]);
       }
     }
 #pragma unroll
