@@ -108,7 +108,13 @@ __device__ __forceinline__ void face_flux_3d(const Phys<T>& ph, const T* __restr
     }
     core_flux(ph, D, UL, UR, Hc, vl[q], vr[q], ha[q], bad);
 #pragma unroll
-    for (int f = 0; f < NF_CORE; ++f) hc[f][q] = Hc[f];
+    for (int f = 0; f < NF_CORE; ++f) {
+      hc[f][q] = Hc[f];
+      keep_order(hc[f][q]);
+    }
+    keep_order(vl[q]);
+    keep_order(vr[q]);
+    keep_order(ha[q]);
   }
 #pragma unroll
   for (int f = 0; f < NF_CORE; ++f) H[f] = simpson9(hc[f]);
@@ -124,6 +130,7 @@ __device__ __forceinline__ void face_flux_3d(const Phys<T>& ph, const T* __restr
       h[q] = T(0.5) * (ul * vl[q] + ur * vr[q]) - ha[q] * (ur - ul);
     }
     H[f] = simpson9(h);
+    keep_order(H[f]);
   }
 }
 
