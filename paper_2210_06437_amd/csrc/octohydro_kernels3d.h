@@ -831,12 +831,13 @@ __device__ __forceinline__ void ws_column(const GridArgs& g, const Phys<T>& ph,
   }
 }
 
-// Work of each wavefront (measured in clocks, the four finish their tasks
-// within 8 % of each other at 11 binary64 fields; a plane task is about an
-// eighth of a wavefront's work, so no other split does better):
-//   0: z-faces 4..8, y-face 8, y-face plane 7
-//   1: z-faces 0..3, x-face 0, y-face planes 5, 6
-//   2: x-face 8, y-face 0, y-face planes 0..4
+// Work of each wavefront, in this order (measured in clocks, the four
+// finish their tasks within 4 % of each other at 11 binary64 fields; a plane
+// task is about an eighth of a wavefront's work, so no other split does
+// better; the boundary faces, which span the whole tile, come last):
+//   0: z-faces 4..8, y-face plane 7, y-face 8
+//   1: z-faces 0..3, y-face planes 5, 6, x-face 0
+//   2: y-face planes 0..4, x-face 8, y-face 0
 //   3: x-face planes 0..7
 // written out per wavefront, not as a list of tasks in one loop: in a loop
 // the compiler keeps every task's loop-invariant values in registers
@@ -866,12 +867,12 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
   } else {
     if (wave < 2)
       ws_column<T, NF>(g, ph, Gt, fsG, leaf, wave == 0 ? 4 : 0, wave == 0 ? SUB : 3, lane, Hs, bad);
-    const int k0 = wave == 0 ? 3 : (wave == 1 ? 0 : 1), k1 = wave == 2 ? 2 : k0;
-#pragma unroll 1
-    for (int k = k0; k <= k1; ++k) ws_boundary<T, NF>(g, ph, Gt, fsG, leaf, k, lane, Hs, bad);
     const int z0 = wave == 0 ? 7 : (wave == 1 ? 5 : 0), z1 = wave == 0 ? 7 : (wave == 1 ? 6 : 4);
 #pragma unroll 1
     for (int z = z0; z <= z1; ++z) ws_plane<T, NF, 1>(ph, Gt, fsG, z, lane, Hs, bad);
+    const int k0 = wave == 0 ? 3 : (wave == 1 ? 0 : 1), k1 = wave == 2 ? 2 : k0;
+#pragma unroll 1
+    for (int k = k0; k <= k1; ++k) ws_boundary<T, NF>(g, ph, Gt, fsG, leaf, k, lane, Hs, bad);
   }
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
   __syncthreads();
