@@ -7,11 +7,13 @@ For each (dtype, n_fields) it times every combination of
   - XCD remap: leaves in launch order, one contiguous range per XCD, or
     chunks of 64 or 512 consecutive leaves dealt to the XCDs in turn,
 on a workload of the benchmark's shape (the later-stage substep, which reads
-U0), through the C-ABI, and records the fastest in ``tuning.json`` next to
-this file with every measured variant; then, in the chosen shape and on
-whole chained RK3 steps, whether the last substep takes the next CFL minimum
-in its kernel or in a pass over its output, and whether the substeps leave
-the restricted node copies of their outputs or passes make them.  Every choice computes the same bits.
+U0), through the C-ABI; then, in the fastest leaf shape and XCD remap and on
+whole chained RK3 steps, every combination of the register budget, whether
+the last substep takes the next CFL minimum in its kernel or in a pass over
+its output, and whether the substeps leave the restricted node copies of
+their outputs or passes make them.  It records the fastest whole step in
+``tuning.json`` next to this file, with every measured variant.  Every
+choice computes the same bits.
 ``binding.py`` applies the recorded choices when it is imported.
 
 Run on the GPU:  python -m paper_2210_06437_amd.autotune [--quick]
@@ -75,38 +77,48 @@ def tune_workload(torch, w, dtype, reps=5):
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_SIMD, best["waves_per_simd"])
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_LEAF, best["waves_per_leaf"])
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_XCD_REMAP, best["xcd_remap"])
-    # in the chosen shape, the RK3 step's own choices, timed on whole
-    # chained RK3 steps: where the next CFL minimum is taken (the last
-    # substep's kernel, or a pass over its output) and where the node copies
-    # are made (left by the substeps, or a pass before each)
+    # in the chosen leaf shape and leaf placement, the RK3 step's own
+    # choices, timed on whole chained RK3 steps: where the next CFL minimum is
+    # taken (the last substep's kernel, or a pass over its output), where the
+    # node copies are made (left by the substeps, or a pass before each), and
+    # the register budget again, since the kernels that take the CFL minimum
+    # or leave the node copies need more registers than the plain one (binary32
+    # at 11 fields: 271 for the CFL variant against 248, one wavefront per SIMD
+    # instead of two unless held to 256)
     step_grid = hb.Grid(w.leaf_coord, w.base, w.nf, dtype, cfl_epilogue=True)
     X = torch.from_numpy(w.U).to("cuda").to(tdt).contiguous()
     Y, W1, W2 = step_grid.empty_state(), step_grid.empty_state(), step_grid.empty_state()
     dt2 = torch.zeros(2, dtype=torch.float64, device="cuda")
     hb.hydro_cfl_dt(step_grid, X, 0.0, dt2[1:])
     step = []
-    for epi in (1, 0):
-        for fr in (1, 0):
-            hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_CFL_EPILOGUE, epi)
-            hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_FUSED_RESTRICT, fr)
-            best_ms = float("inf")
-            for i in range(reps + 1):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-                hb.hydro_rk3_step(step_grid, X, W1, W2, Y, w.cfl, dt2)
-                e1.record()
-                torch.cuda.synchronize()
-                X, Y = Y, X
-                if i:
-                    best_ms = min(best_ms, e0.elapsed_time(e1))
-            step.append({"cfl_epilogue": epi, "fused_restrict": fr, "ms": best_ms})
-            print(f"[autotune] dtype={dtype} nf={w.nf} RK3 step, CFL "
-                  f"{'in the kernel' if epi else 'in a pass'}, node copies "
-                  f"{'by the substeps' if fr else 'in passes'}: {best_ms:.3f} ms",
-                  file=sys.stderr, flush=True)
+    budgets = (1, 2) if best["waves_per_leaf"] == 1 else (best["waves_per_simd"],)
+    for waves in budgets:
+        for epi in (1, 0):
+            for fr in (1, 0):
+                hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_SIMD, waves)
+                hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_CFL_EPILOGUE, epi)
+                hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_FUSED_RESTRICT, fr)
+                best_ms = float("inf")
+                for i in range(reps + 1):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    hb.hydro_rk3_step(step_grid, X, W1, W2, Y, w.cfl, dt2)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    X, Y = Y, X
+                    if i:
+                        best_ms = min(best_ms, e0.elapsed_time(e1))
+                step.append({"waves_per_simd": waves, "cfl_epilogue": epi, "fused_restrict": fr,
+                             "ms": best_ms})
+                print(f"[autotune] dtype={dtype} nf={w.nf} RK3 step, waves/SIMD={waves}, CFL "
+                      f"{'in the kernel' if epi else 'in a pass'}, node copies "
+                      f"{'by the substeps' if fr else 'in passes'}: {best_ms:.3f} ms",
+                      file=sys.stderr, flush=True)
     pick = min(step, key=lambda r: r["ms"])
     epi, fr = pick["cfl_epilogue"], pick["fused_restrict"]
+    best["waves_per_simd"] = pick["waves_per_simd"]
+    hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_WAVES_PER_SIMD, pick["waves_per_simd"])
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_CFL_EPILOGUE, epi)
     hb.hydro_set_option(dtype, w.nf, hb.HYDRO_OPT_FUSED_RESTRICT, fr)
     del X, Y, W1, W2, step_grid

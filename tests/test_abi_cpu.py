@@ -182,9 +182,18 @@ def test_recorded_tuning_is_well_formed(hb):
         r = e["xcd_remap"]
         assert r in (0, 1) or (2 <= r <= 4096 and r & (r - 1) == 0)
         assert 6 <= e["n_fields"] <= 16 and e["dtype"] in (0, 1)
-        # every measured variant is recorded, and the choice is the fastest
+        # every measured variant is recorded; the leaf shape and remap are
+        # those of the fastest substep, the rest that of the fastest RK3 step
         assert len(e["all"]) >= 8
         assert e["ms"] == min(v["ms"] for v in e["all"])
+        fastest = min(e["all"], key=lambda v: v["ms"])
+        assert (e["waves_per_leaf"], e["xcd_remap"]) == (fastest["waves_per_leaf"],
+                                                         fastest["xcd_remap"])
+        if "rk3_step" in e:
+            pick = min(e["rk3_step"], key=lambda v: v["ms"])
+            assert (e["cfl_epilogue"], e["fused_restrict"]) == (pick["cfl_epilogue"],
+                                                                pick["fused_restrict"])
+            assert e["waves_per_simd"] == pick.get("waves_per_simd", e["waves_per_simd"])
 
 
 def test_product_path_has_no_oracle_dependency():
