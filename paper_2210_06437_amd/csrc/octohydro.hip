@@ -347,8 +347,8 @@ static int grid_blocks(int64_t work, int threads, int cap) {
 // contiguous rows.
 template <typename T>
 __global__ void __launch_bounds__(256) k_fill(GridArgs g, const T* __restrict__ U,
-                                              T* __restrict__ G) {
-  const int leaf = blockIdx.x;
+                                              T* __restrict__ G, int remap) {
+  const int leaf = leaf_of_block(blockIdx.x, g.n_leaves, remap);
   const int4 c4 = reinterpret_cast<const int4*>(g.coord)[leaf];
   const int ic[3] = {c4.y, c4.z, c4.w};
   const int blocks = g.base << c4.x;
@@ -396,14 +396,19 @@ __global__ void __launch_bounds__(256) k_fill(GridArgs g, const T* __restrict__ 
 }
 
 // Ghosted 14^3 tiles of U into G (all 26 ghost regions).
+// Leaves go to the XCDs in contiguous Morton ranges (remap mode 1), so that a
+// tile's neighbour cells are mostly read on the XCD that reads them for the
+// neighbour's own tile: 8.12 -> 7.85 ms per binary64 fill of the 65535-leaf
+// case (binary32 unchanged).
+constexpr int FILL_REMAP = 1;
 static int fill_launch(const hydro_grid* gr, const void* U, void* G, hipStream_t st) {
   const GridArgs g = grid_args(gr);
   if (gr->dtype == HYDRO_F64)
     hipLaunchKernelGGL(k_fill<double>, dim3(g.n_leaves), dim3(256), 0, st, g,
-                       static_cast<const double*>(U), static_cast<double*>(G));
+                       static_cast<const double*>(U), static_cast<double*>(G), FILL_REMAP);
   else
     hipLaunchKernelGGL(k_fill<float>, dim3(g.n_leaves), dim3(256), 0, st, g,
-                       static_cast<const float*>(U), static_cast<float*>(G));
+                       static_cast<const float*>(U), static_cast<float*>(G), FILL_REMAP);
   HIP_TRY(hipGetLastError());
   return HYDRO_OK;
 }
