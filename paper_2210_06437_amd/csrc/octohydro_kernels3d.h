@@ -842,10 +842,11 @@ __device__ __forceinline__ void ws_column(const GridArgs& g, const Phys<T>& ph,
 // written out per wavefront, not as a list of tasks in one loop: in a loop
 // the compiler keeps every task's loop-invariant values in registers
 // through all of them.
-// binary32 at two workgroups per CU (256 registers; its flux store is 77 KB
-// at 11 fields), binary64 at one.
+// binary32 at two workgroups per CU where two flux stores fit in LDS (256
+// registers; the store is 77 KB at 11 fields), binary64 at one.
 template <typename T, int NF>
-__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 && 2 * ws3d_lds_bytes<T, NF>() <= 160 * 1024)
+                                           ? 2 : 1)
     k_step3d_ws(StepArgs s, const T* __restrict__ G) {
   __shared__ T Hs[WS_PLANES][NF][64];  // the layout of k_step3d_wg and a spare plane
   const GridArgs& g = s.g;
