@@ -523,28 +523,29 @@ __global__ void __launch_bounds__(256, 1) k_step3d_wg(StepArgs s, const T* __res
 // workgroup, flux store and cell finishing of k_step3d_wg, with face fluxes
 // from tasks that reconstruct each (cell, line) once per face orientation
 // and use both ends of its parabola.
-//  - Plane task (D, z), D = x or y: lane (x, y) holds cell (x, y, z).  The
-//    faces normal to D use the 9 lines e(a, b) = D + a u + b v, where u < v
-//    are the face's transverse axes and a, b are in {-1, 0, 1}.  Face c - 1/2
-//    along D takes at point (a, b) the right end of e(a, b) of the cell
-//    below it (the lane before along D: a DPP shift of one lane for x, a
-//    shuffle of 8 lanes for y) as its left state, and the left end of
-//    e(-a, -b) of its own cell as its right state.  Each lane with c >= 1
-//    gets one face; faces 0 and 8 come from the boundary tasks.
+//  - Plane task (z): lane (x, y) holds cell (x, y, z) and evaluates its low
+//    x-face and its low y-face.  A face point takes an end of a line of the
+//    cell below along the face normal (the lane before: a DPP shift of one
+//    lane for x, a shuffle of 8 lanes for y) as its left state and an end of
+//    a line of its own cell as its right state.  The 12 lines with an x or y
+//    component serve both orientations: each is reconstructed once (18 for
+//    the two orientations apart).  Lanes at x = 0 (y = 0) have no x-face
+//    (y-face) of theirs; faces 0 and 8 come from the boundary tasks.
 //  - Boundary task: face 0 or face 8 along x or y for the whole leaf, one
 //    face per lane, evaluated as in k_step3d_wg (both sides' line ends).
 //  - Column task: lane (x, y) walks up its column, carrying the right ends
 //    of the 9 lines a x + b y + z of the cell below; face c - 1/2 takes the
 //    carried end of e(a, b) and the left end of e(-a, -b) of cell c at point
 //    (a, b).  Two tasks split the column: faces 0..3 and 4..8.
-// The lines are walked in the direction of the face normal, not always in
-// the canonical direction of the point, and parabola() gives the same ends
-// either way.  The points are taken in pairs (a, b) and (-a, -b), whose two
-// lines give both points' states, in the order of the Simpson sums, so each
-// face's flux is the sequence of operations face_flux_3d performs: the same
-// bits.  Each pair's results are kept in program order (keep_order): without
-// that the plane task at 11 binary64 fields spilled 248 VGPRs, with it it
-// takes 300 and spills none.
+// The column task walks its lines in the direction of the face normal, not
+// always in the canonical direction of the point, and parabola() gives the
+// same ends either way.  The points are taken in pairs (a, b) and (-a, -b),
+// whose two lines give both points' states, or in the plane task by line
+// group, in the order of the Simpson sums, so each face's flux is the
+// sequence of operations face_flux_3d performs: the same bits.  Each group's
+// results are kept in program order (keep_order): without that a
+// single-orientation plane task at 11 binary64 fields spilled 248 VGPRs,
+// with it it took 300 and spilled none.
 // ---------------------------------------------------------------------------
 
 // The flux store of k_step3d_ws: k_step3d_wg's 27 planes and a spare one
@@ -608,86 +609,224 @@ __device__ __forceinline__ T passive_flux(T ul, T ur, T vl, T vr, T ha) {
   return T(0.5) * (ul * vl + ur * vr) - ha * (ur - ul);
 }
 
-// Plane task: faces 1..7 along D (0: x, 1: y) of cell plane z into Hs.
-// The core fields go first over all point pairs and leave each point's
-// velocities and half signal speed (point slot 2p: (a, b), 2p + 1:
-// (-a, -b), 8: the centre); each species then goes over the pairs on its
-// own, so only one species' line ends are held at a time.
-template <typename T, int NF, int D>
-__device__ __forceinline__ void ws_plane(const Phys<T>& ph, const T* __restrict__ Gt, size_t fsG,
-                                         int z, int lane, T (&Hs)[WS_PLANES][NF][64],
-                                         bool& bad) {
-  constexpr int SD = D == 0 ? 1 : TW;       // tile stride along D
-  constexpr int SU = D == 0 ? TW : 1;       // along u (y for x-faces, x for y-faces)
-  constexpr int SV = TW * TW;               // along v (z)
+// Plane task: faces 1..7 along x and along y of cell plane z into Hs, lane
+// (x, y) holding cell (x, y, z), with the lines that serve both orientations
+// reconstructed once:
+//   body diagonals L0 (1,1,1), L1 (1,-1,-1), L2 (1,1,-1), L3 (1,-1,1): the
+//     corner points of the x-faces and of the y-faces;
+//   M0 (1,0,1), M1 (1,0,-1): the x-faces' edge points (0, +-1);
+//   N0 (0,1,1), N1 (0,1,-1): the y-faces' edge points (0, +-1);
+//   P0 (1,1,0), P1 (1,-1,0): the edge points (+-1, 0) of both;
+//   (1,0,0) and (0,1,0): the centres.
+// 12 reconstructions per cell for the two orientations instead of 18.  A
+// point's left state is an end of the cell below along the face normal (x:
+// a DPP shift of one lane, y: a shuffle of 8 lanes), its right state an end
+// of its own cell; which end follows from the line's canonical direction.
+template <typename T>
+struct XYAcc {
+  T xc, yc, xe, ye;  // corner and edge sums of the x- and y-face
+};
+
+template <typename T, int NF>
+__device__ __forceinline__ void ws_plane_xy(const Phys<T>& ph, const T* __restrict__ Gt,
+                                            size_t fsG, int z, int lane,
+                                            T (&Hs)[WS_PLANES][NF][64], bool& bad) {
+  constexpr int SX = 1, SY = TW, SZ = TW * TW;
   const int x = lane & 7, y = lane >> 3;
   const int t = tile_at(x, y, z);
-  T sa[NF_CORE], sb[NF_CORE], H[NF];
-  T vl[9], vr[9], ha[9];
-  bool b2 = false;
+  XYAcc<T> acc[NF];
+  T Hx[NF], Hy[NF];
+  bool bx = false, by = false;
+  // ---- body diagonals: corners of both orientations
+  {
+    constexpr int s0 = SX + SY + SZ, s1 = SX - SY - SZ, s2 = SX + SY - SZ, s3 = SX - SY + SZ;
+    T vl[8], vr[8], ha[8];  // points: x (1,1) (-1,-1) (1,-1) (-1,1), y the same
+    {
+      T xL[4][NF_CORE], xR[4][NF_CORE], yL[4][NF_CORE], yR[4][NF_CORE];
 #pragma unroll
-  for (int p = 0; p < 5; ++p) {
-    const int sA = SD + WS_PA[p] * SU + WS_PB[p] * SV;  // line e(a, b)
-    const int sB = SD - WS_PA[p] * SU - WS_PB[p] * SV;  // line e(-a, -b)
-    T ULp[NF_CORE], URp[NF_CORE], ULm[NF_CORE], URm[NF_CORE];
+      for (int f = 0; f < NF_CORE; ++f) {
+        T l0, h0, l1, h1, l2, h2, l3, h3;
+        const T* q = Gt + f * fsG + t;
+        parabola(q, s0, l0, h0);
+        parabola(q, s1, l1, h1);
+        parabola(q, s2, l2, h2);
+        parabola(q, s3, l3, h3);
+        xL[0][f] = prev_cell<0>(h0); xR[0][f] = l1;  // x (1,1)
+        xL[1][f] = prev_cell<0>(h1); xR[1][f] = l0;  // x (-1,-1)
+        xL[2][f] = prev_cell<0>(h2); xR[2][f] = l3;  // x (1,-1)
+        xL[3][f] = prev_cell<0>(h3); xR[3][f] = l2;  // x (-1,1)
+        yL[0][f] = prev_cell<1>(h0); yR[0][f] = h3;  // y (1,1)
+        yL[1][f] = prev_cell<1>(l3); yR[1][f] = l0;  // y (-1,-1)
+        yL[2][f] = prev_cell<1>(h2); yR[2][f] = h1;  // y (1,-1)
+        yL[3][f] = prev_cell<1>(l1); yR[3][f] = l2;  // y (-1,1)
+      }
+      T hx[4][NF_CORE], hy[4][NF_CORE];
 #pragma unroll
-    for (int f = 0; f < NF_CORE; ++f) {
-      T lA, rA;
-      parabola(Gt + f * fsG + t, sA, lA, rA);
-      ULp[f] = prev_cell<D>(rA);
-      if (p < 4) {
-        T lB, rB;
-        parabola(Gt + f * fsG + t, sB, lB, rB);
-        URp[f] = lB;
-        ULm[f] = prev_cell<D>(rB);
-        URm[f] = lA;
-      } else {
-        URp[f] = lA;
+      for (int q = 0; q < 4; ++q) {
+        core_flux(ph, 0, xL[q], xR[q], hx[q], vl[q], vr[q], ha[q], bx);
+        core_flux(ph, 1, yL[q], yR[q], hy[q], vl[4 + q], vr[4 + q], ha[4 + q], by);
+      }
+#pragma unroll
+      for (int f = 0; f < NF_CORE; ++f) {
+        acc[f].xc = (hx[1][f] + hx[0][f]) + (hx[2][f] + hx[3][f]);
+        acc[f].yc = (hy[1][f] + hy[0][f]) + (hy[2][f] + hy[3][f]);
+        keep_order(acc[f].xc);
+        keep_order(acc[f].yc);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        keep_order(vl[q]);
+        keep_order(vr[q]);
+        keep_order(ha[q]);
       }
     }
-    T Hp[NF_CORE], Hm[NF_CORE];
-    core_flux(ph, D, ULp, URp, Hp, vl[2 * p], vr[2 * p], ha[2 * p], b2);
-    if (p < 4) core_flux(ph, D, ULm, URm, Hm, vl[2 * p + 1], vr[2 * p + 1], ha[2 * p + 1], b2);
 #pragma unroll
-    for (int f = 0; f < NF_CORE; ++f) {
-      simpson_pair(p, Hp[f], p < 4 ? Hm[f] : T(0), sa[f], sb[f], H[f]);
-      keep_order(p < 2 ? sa[f] : (p < 4 ? sb[f] : H[f]));
-    }
-    keep_order(vl[2 * p]);
-    keep_order(vr[2 * p]);
-    keep_order(ha[2 * p]);
-    if (p < 4) {
-      keep_order(vl[2 * p + 1]);
-      keep_order(vr[2 * p + 1]);
-      keep_order(ha[2 * p + 1]);
+    for (int f = NF_CORE; f < NF; ++f) {
+      T l0, h0, l1, h1, l2, h2, l3, h3;
+      const T* q = Gt + f * fsG + t;
+      parabola(q, s0, l0, h0);
+      parabola(q, s1, l1, h1);
+      parabola(q, s2, l2, h2);
+      parabola(q, s3, l3, h3);
+      const T x0 = passive_flux(prev_cell<0>(h0), l1, vl[0], vr[0], ha[0]);
+      const T x1 = passive_flux(prev_cell<0>(h1), l0, vl[1], vr[1], ha[1]);
+      const T x2 = passive_flux(prev_cell<0>(h2), l3, vl[2], vr[2], ha[2]);
+      const T x3 = passive_flux(prev_cell<0>(h3), l2, vl[3], vr[3], ha[3]);
+      const T y0 = passive_flux(prev_cell<1>(h0), h3, vl[4], vr[4], ha[4]);
+      const T y1 = passive_flux(prev_cell<1>(l3), l0, vl[5], vr[5], ha[5]);
+      const T y2 = passive_flux(prev_cell<1>(h2), h1, vl[6], vr[6], ha[6]);
+      const T y3 = passive_flux(prev_cell<1>(l1), l2, vl[7], vr[7], ha[7]);
+      acc[f].xc = (x1 + x0) + (x2 + x3);
+      acc[f].yc = (y1 + y0) + (y2 + y3);
+      keep_order(acc[f].xc);
+      keep_order(acc[f].yc);
     }
   }
+  // ---- two-line groups: edges.  G = 0: M (x-faces' (0, +-1)), G = 1: N
+  // (y-faces' (0, +-1)), G = 2: P ((+-1, 0) of both)
 #pragma unroll
-  for (int f = NF_CORE; f < NF; ++f) {
-    T fa = T(0), fb = T(0);
+  for (int G = 0; G < 3; ++G) {
+    const int sA = G == 0 ? SX + SZ : (G == 1 ? SY + SZ : SX + SY);
+    const int sB = G == 0 ? SX - SZ : (G == 1 ? SY - SZ : SX - SY);
+    // points per group: M: x (0,-1) [L hi(M1)@x-1, R lo(M0)], x (0,1) [L hi(M0)@x-1, R lo(M1)]
+    //                   N: y (0,-1) [L hi(N1)@y-1, R lo(N0)], y (0,1) [L hi(N0)@y-1, R lo(N1)]
+    //                   P: x (-1,0) [L hi(P1)@x-1, R lo(P0)], x (1,0) [L hi(P0)@x-1, R lo(P1)],
+    //                      y (-1,0) [L lo(P1)@y-1, R lo(P0)], y (1,0) [L hi(P0)@y-1, R hi(P1)]
+    constexpr int NP = 4;
+    T vl[NP], vr[NP], ha[NP];
+    {
+      T L[NP][NF_CORE], R[NP][NF_CORE];
 #pragma unroll
-    for (int p = 0; p < 5; ++p) {
-      const int sA = SD + WS_PA[p] * SU + WS_PB[p] * SV;
-      const int sB = SD - WS_PA[p] * SU - WS_PB[p] * SV;
-      T lA, rA, hp, hm = T(0);
-      parabola(Gt + f * fsG + t, sA, lA, rA);
-      if (p < 4) {
-        T lB, rB;
-        parabola(Gt + f * fsG + t, sB, lB, rB);
-        hp = passive_flux(prev_cell<D>(rA), lB, vl[2 * p], vr[2 * p], ha[2 * p]);
-        hm = passive_flux(prev_cell<D>(rB), lA, vl[2 * p + 1], vr[2 * p + 1], ha[2 * p + 1]);
-      } else {
-        hp = passive_flux(prev_cell<D>(rA), lA, vl[2 * p], vr[2 * p], ha[2 * p]);
+      for (int f = 0; f < NF_CORE; ++f) {
+        T lA, hA, lB, hB;
+        const T* q = Gt + f * fsG + t;
+        parabola(q, sA, lA, hA);
+        parabola(q, sB, lB, hB);
+        if (G == 0) {
+          L[0][f] = prev_cell<0>(hB); R[0][f] = lA;
+          L[1][f] = prev_cell<0>(hA); R[1][f] = lB;
+        } else if (G == 1) {
+          L[0][f] = prev_cell<1>(hB); R[0][f] = lA;
+          L[1][f] = prev_cell<1>(hA); R[1][f] = lB;
+        } else {
+          L[0][f] = prev_cell<0>(hB); R[0][f] = lA;
+          L[1][f] = prev_cell<0>(hA); R[1][f] = lB;
+          L[2][f] = prev_cell<1>(lB); R[2][f] = lA;
+          L[3][f] = prev_cell<1>(hA); R[3][f] = hB;
+        }
       }
-      simpson_pair(p, hp, hm, fa, fb, H[f]);
-      keep_order(p < 2 ? fa : (p < 4 ? fb : H[f]));
+      T h[NP][NF_CORE];
+#pragma unroll
+      for (int q = 0; q < (G == 2 ? 4 : 2); ++q) {
+        const int D = G == 0 ? 0 : (G == 1 ? 1 : (q < 2 ? 0 : 1));
+        core_flux(ph, D, L[q], R[q], h[q], vl[q], vr[q], ha[q], D == 0 ? bx : by);
+      }
+#pragma unroll
+      for (int f = 0; f < NF_CORE; ++f) {
+        if (G == 0) acc[f].xe = h[0][f] + h[1][f];
+        else if (G == 1) acc[f].ye = h[0][f] + h[1][f];
+        else {
+          acc[f].xe = acc[f].xe + (h[0][f] + h[1][f]);
+          acc[f].ye = acc[f].ye + (h[2][f] + h[3][f]);
+        }
+        keep_order(acc[f].xe);
+        keep_order(acc[f].ye);
+      }
+#pragma unroll
+      for (int q = 0; q < (G == 2 ? 4 : 2); ++q) {
+        keep_order(vl[q]);
+        keep_order(vr[q]);
+        keep_order(ha[q]);
+      }
+    }
+#pragma unroll
+    for (int f = NF_CORE; f < NF; ++f) {
+      T lA, hA, lB, hB;
+      const T* q = Gt + f * fsG + t;
+      parabola(q, sA, lA, hA);
+      parabola(q, sB, lB, hB);
+      if (G == 0) {
+        acc[f].xe = passive_flux(prev_cell<0>(hB), lA, vl[0], vr[0], ha[0]) +
+                    passive_flux(prev_cell<0>(hA), lB, vl[1], vr[1], ha[1]);
+      } else if (G == 1) {
+        acc[f].ye = passive_flux(prev_cell<1>(hB), lA, vl[0], vr[0], ha[0]) +
+                    passive_flux(prev_cell<1>(hA), lB, vl[1], vr[1], ha[1]);
+      } else {
+        acc[f].xe = acc[f].xe + (passive_flux(prev_cell<0>(hB), lA, vl[0], vr[0], ha[0]) +
+                                 passive_flux(prev_cell<0>(hA), lB, vl[1], vr[1], ha[1]));
+        acc[f].ye = acc[f].ye + (passive_flux(prev_cell<1>(lB), lA, vl[2], vr[2], ha[2]) +
+                                 passive_flux(prev_cell<1>(hA), hB, vl[3], vr[3], ha[3]));
+      }
+      keep_order(acc[f].xe);
+      keep_order(acc[f].ye);
     }
   }
-  const bool has_face = (D == 0 ? x : y) != 0;
-  bad |= b2 && has_face;
-  const int slot = has_face ? (D == 0 ? 0 : 9) + z : WS_SPARE;
+  // ---- centres: (1,0,0) for x, (0,1,0) for y
+  {
+    T vlx, vrx, hax, vly, vry, hay;
+    {
+      T XL[NF_CORE], XR[NF_CORE], YL[NF_CORE], YR[NF_CORE], hx[NF_CORE], hy[NF_CORE];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) Hs[slot][f][lane] = H[f];
+      for (int f = 0; f < NF_CORE; ++f) {
+        T lx, hxe, ly, hye;
+        const T* q = Gt + f * fsG + t;
+        parabola(q, SX, lx, hxe);
+        parabola(q, SY, ly, hye);
+        XL[f] = prev_cell<0>(hxe); XR[f] = lx;
+        YL[f] = prev_cell<1>(hye); YR[f] = ly;
+      }
+      core_flux(ph, 0, XL, XR, hx, vlx, vrx, hax, bx);
+      core_flux(ph, 1, YL, YR, hy, vly, vry, hay, by);
+#pragma unroll
+      for (int f = 0; f < NF_CORE; ++f) {
+        Hx[f] = ((acc[f].xc + T(4) * acc[f].xe) + T(16) * hx[f]) / T(36);
+        Hy[f] = ((acc[f].yc + T(4) * acc[f].ye) + T(16) * hy[f]) / T(36);
+        keep_order(Hx[f]);
+        keep_order(Hy[f]);
+      }
+      keep_order(vlx); keep_order(vrx); keep_order(hax);
+      keep_order(vly); keep_order(vry); keep_order(hay);
+    }
+#pragma unroll
+    for (int f = NF_CORE; f < NF; ++f) {
+      T lx, hxe, ly, hye;
+      const T* q = Gt + f * fsG + t;
+      parabola(q, SX, lx, hxe);
+      parabola(q, SY, ly, hye);
+      const T cx = passive_flux(prev_cell<0>(hxe), lx, vlx, vrx, hax);
+      const T cy = passive_flux(prev_cell<1>(hye), ly, vly, vry, hay);
+      Hx[f] = ((acc[f].xc + T(4) * acc[f].xe) + T(16) * cx) / T(36);
+      Hy[f] = ((acc[f].yc + T(4) * acc[f].ye) + T(16) * cy) / T(36);
+      keep_order(Hx[f]);
+      keep_order(Hy[f]);
+    }
+  }
+  bad |= (bx && x != 0) || (by && y != 0);
+  const int sx = x != 0 ? z : WS_SPARE, sy = y != 0 ? 9 + z : WS_SPARE;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) Hs[sx][f][lane] = Hx[f];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) Hs[sy][f][lane] = Hy[f];
 }
 
 // Boundary task k (0: x-face 0, 1: x-face 8, 2: y-face 0, 3: y-face 8):
@@ -831,14 +970,14 @@ __device__ __forceinline__ void ws_column(const GridArgs& g, const Phys<T>& ph,
   }
 }
 
-// Work of each wavefront, in this order (measured in clocks, the four
-// finish their tasks within 4 % of each other at 11 binary64 fields; a plane
-// task is about an eighth of a wavefront's work, so no other split does
-// better; the boundary faces, which span the whole tile, come last):
-//   0: z-faces 4..8, y-face plane 7, y-face 8
-//   1: z-faces 0..3, y-face planes 5, 6, x-face 0
-//   2: y-face planes 0..4, x-face 8, y-face 0
-//   3: x-face planes 0..7
+// Work of each wavefront, in this order (the boundary faces, which span the
+// whole tile, come last; by VALU instructions at 11 binary64 fields the
+// lists are 68 k, 58 k, 69 k and 70 k, and no other split of these tasks
+// does better):
+//   0: z-faces 4..8, y-face 8
+//   1: z-faces 0..3, plane 7
+//   2: planes 0..3, x-face 8
+//   3: planes 4..6, x-face 0, y-face 0
 // written out per wavefront, not as a list of tasks in one loop: in a loop
 // the compiler keeps every task's loop-invariant values in registers
 // through all of them.
@@ -862,19 +1001,17 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && 2 * ws3d_lds_bytes<T, 
   const size_t fsG = (size_t)g.n_leaves * TILE;
   const T* __restrict__ Gt = G + (size_t)leaf * TILE;
   bool bad = false;
-  if (wave == 3) {
+  if (wave < 2)
+    ws_column<T, NF>(g, ph, Gt, fsG, leaf, wave == 0 ? 4 : 0, wave == 0 ? SUB : 3, lane, Hs, bad);
+  const int z0 = wave == 1 ? 7 : (wave == 2 ? 0 : 4);
+  const int z1 = wave == 0 ? -1 : (wave == 1 ? 7 : (wave == 2 ? 3 : 6));
 #pragma unroll 1
-    for (int z = 0; z < SUB; ++z) ws_plane<T, NF, 0>(ph, Gt, fsG, z, lane, Hs, bad);
-  } else {
-    if (wave < 2)
-      ws_column<T, NF>(g, ph, Gt, fsG, leaf, wave == 0 ? 4 : 0, wave == 0 ? SUB : 3, lane, Hs, bad);
-    const int z0 = wave == 0 ? 7 : (wave == 1 ? 5 : 0), z1 = wave == 0 ? 7 : (wave == 1 ? 6 : 4);
+  for (int z = z0; z <= z1; ++z) ws_plane_xy<T, NF>(ph, Gt, fsG, z, lane, Hs, bad);
+  // boundary tasks k0, k0 + 2, ... up to k1
+  const int k0 = wave == 0 ? 3 : (wave == 3 ? 0 : 1);
+  const int k1 = wave == 0 ? 3 : (wave == 1 ? 0 : (wave == 2 ? 1 : 2));
 #pragma unroll 1
-    for (int z = z0; z <= z1; ++z) ws_plane<T, NF, 1>(ph, Gt, fsG, z, lane, Hs, bad);
-    const int k0 = wave == 0 ? 3 : (wave == 1 ? 0 : 1), k1 = wave == 2 ? 2 : k0;
-#pragma unroll 1
-    for (int k = k0; k <= k1; ++k) ws_boundary<T, NF>(g, ph, Gt, fsG, leaf, k, lane, Hs, bad);
-  }
+  for (int k = k0; k <= k1; k += 2) ws_boundary<T, NF>(g, ph, Gt, fsG, leaf, k, lane, Hs, bad);
   if (g.status && __any(bad) && lane == 0) atomicOr(g.status, (int)HYDRO_STATUS_UNPHYSICAL);
   __syncthreads();
   finish_leaf_3d<T, NF, WS_PLANES>(s, Hs, leaf, c4);
