@@ -788,8 +788,12 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
 
 // Phase Z of half h: lane (x, y) streams its z-pencil over stream positions
 // [4h, 4h+10), which yields the z-faces of cells z in [4h, 4h+4), adds dHz
-// to the accumulator and finishes those cells.
-template <typename T, int NF, int MODE>
+// to the accumulator and finishes those cells.  ZU: unroll factor of the
+// stream loop.  Unrolled by 2, consecutive steps keep the stream state in
+// alternating registers instead of copying it back at every step: with the
+// 512-register budget that was 2-3 % faster in binary64 (the same bits); at
+// two wavefronts per SIMD it was 1 % slower.
+template <typename T, int NF, int MODE, int ZU>
 __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
                                         const FaceNbr& fn, double* __restrict__ acc, int h,
                                         int lane, double dt, double inv_dx, bool& bad,
@@ -815,7 +819,7 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
   stream_prologue<T, NF>(st, S, p, k0);
   T qnext[NF];
   load_position<T, NF>(S, pencil_src(p, k0 + 5), qnext);
-#pragma unroll 1
+#pragma unroll ZU
   for (int kk = 5; kk < 10; ++kk) {
     const int k = k0 + kk;
     T qn[NF];
@@ -932,7 +936,7 @@ __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
   for (int h = 0; h < 2; ++h) {
     phase_xy<T, NF>(s, ph, li, fxy, acc, h, lane, bad);
     wave_lds_sync();
-    phase_z<T, NF, MODE>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad, cflmin, lnode);
+    phase_z<T, NF, MODE, W == 1 ? 2 : 1>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad, cflmin, lnode);
     wave_lds_sync();
   }
   if constexpr (MODE == STEP_CFL) atomic_min_positive(s.dt_next, cflmin, lane);
