@@ -482,7 +482,7 @@ def main():
                    "steps": steps3,
                    "kernel": "k_step3d_ws<double,11> (3D reconstruction, 9-point Simpson flux, "
                              "one workgroup per leaf, each (cell, line) reconstructed once "
-                             "per face orientation)",
+                             "per face orientation, x- and y-faces sharing their common lines)",
                    "kernel_ms": kms3, "ghost_fill_ms": fill3, "ops_per_launch": ops3,
                    "alu_frac": ops3 / (kms3 * 1e-3) / ALU_PEAK,
                    "hbm_frac": hbm_bytes_per_leaf_stage(nf, 8, True) * n / (kms3 * 1e-3) / HBM_PEAK}

@@ -368,9 +368,10 @@ const char* hydro_last_error(void);
  *                             (binary64 up to 11 fields, binary32 up to
  *                             16): evaluating each face from both sides'
  *                             line parabolas (1), or reconstructing each
- *                             (cell, line) once per face orientation and
- *                             using both ends of its parabola (2, the
- *                             default)
+ *                             (cell, line) once per face orientation, the
+ *                             lines common to the x- and y-faces once for
+ *                             both, and using both ends of its parabola
+ *                             (2, the default)
  * Every choice computes the same bits.  Options are process-wide and take effect at the next launch (a captured
  * graph keeps the kernel it was captured with).  Host only, thread-safe.
  */
