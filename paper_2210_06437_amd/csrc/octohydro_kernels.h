@@ -25,7 +25,6 @@ constexpr int TILE = TW * TW * TW;
 constexpr int NF_CORE = 6;  // rho, sx, sy, sz, E, tau
 constexpr int ACC_PITCH = 9;  // LDS row pitch (doubles) of the accumulator
 constexpr int ACC_PLANE = SUB * ACC_PITCH;
-constexpr int ACC_FIELD = SUB * ACC_PLANE;
 // Bound on the byte size of every array the kernels address with 32-bit
 // offsets (buffer resources and 32-bit lane offsets); checked on the host.
 constexpr uint32_t OFF_NONE = 0xFFFFF000u;
@@ -333,7 +332,7 @@ __device__ __forceinline__ float dpp_move(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-template <typename T>
+template <typename T, int PLANE>
 __device__ __forceinline__ void restrict_out(const StepArgs& s, double* __restrict__ slot,
                                              int node, int f, int x, int y, int z, T o) {
   const T t = o + dpp_move<DPP_XOR1>(o);
@@ -341,7 +340,7 @@ __device__ __forceinline__ void restrict_out(const StepArgs& s, double* __restri
   if ((z & 1) == 0) {
     *slot = (double)q;
   } else {
-    const T r = T(0.125) * ((T)slot[-ACC_PLANE] + q);
+    const T r = T(0.125) * ((T)slot[-PLANE] + q);
     if (((x | y) & 1) == 0)
       static_cast<T*>(s.node_out)[((size_t)f * s.g.n_nodes + (node >> 3)) * CELLS +
                                   coarse_cell(node & 7, x, y, z)] = r;
@@ -651,6 +650,20 @@ __device__ __forceinline__ T finish_cell(const StepArgs& s, size_t fbase, uint32
 // LDS accumulator of half a leaf (4 z-planes): field stride ACC_HALF.
 constexpr int ACC_HALF = 4 * ACC_PLANE;
 
+// The same layout with row pitch AP (doubles).  AP = 9, the spare double per
+// row, puts the 8 lanes of an x-pencil group, which add into the same x of 8
+// rows, on distinct LDS banks; AP = 8 takes 11 % less LDS.  With the 256-
+// register budget the accumulator is what limits the workgroups per CU
+// (binary64 at 11 fields: 25.3 KB, 6 per CU; 22.5 KB with AP = 8, 7 per CU):
+// there AP = 8 made the binary32 substep of the 65,535-leaf case 8.5 % faster
+// (3.19 -> 2.92 ms); with the 512-register budget, where registers limit it
+// to 4 per CU, AP = 9 is 0.8 % faster.  The accumulator sums two exact
+// terms, so the layout does not change a bit of the result.
+template <int AP>
+struct AccLayout {
+  static constexpr int PITCH = AP, PLANE = SUB * AP, HALF = 4 * SUB * AP;
+};
+
 // Point after which lanes of a wave read LDS values that other lanes of the
 // same wave wrote.  One wave's LDS instructions execute in program order, so
 // the hardware needs no wait; the wavefront-scope fences (which emit no
@@ -732,7 +745,7 @@ __device__ __forceinline__ void stream_step(const Phys<T>& ph, int d, Ppm<T> (&s
 // binary64 addition (it keeps the sign of a zero term) and a sum of two terms
 // does not depend on their order, so the accumulator holds exactly dHx + dHy
 // whichever lane gets there first, with no branch on the lane.
-template <typename T, int NF>
+template <typename T, int NF, int AP>
 __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
                                          const FaceNbr& fn, double* __restrict__ acc, int h,
                                          int lane, bool& bad) {
@@ -745,10 +758,11 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
   const int a = lane & 7;
   const int zz = (lane >> 3) & 3;
   const Pencil p = make_pencil<T>(g, li, d, a, 4 * h + zz, fn);
-  const int acc_off = d == 0 ? zz * ACC_PLANE + a * ACC_PITCH : zz * ACC_PLANE + a;
-  const int acc_step = d == 0 ? 1 : ACC_PITCH;
+  using L = AccLayout<AP>;
+  const int acc_off = d == 0 ? zz * L::PLANE + a * L::PITCH : zz * L::PLANE + a;
+  const int acc_step = d == 0 ? 1 : L::PITCH;
 
-  for (int j = lane; j < NF * ACC_HALF / 2; j += 64)
+  for (int j = lane; j < NF * L::HALF / 2; j += 64)
     reinterpret_cast<double2*>(acc)[j] = make_double2(-0.0, -0.0);
   wave_lds_sync();
   Ppm<T> st[NF];
@@ -778,7 +792,7 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
       for (int f = 0; f < NF; ++f) dH[f] = (double)H[f] - Hprev[f];
 #pragma unroll
       for (int f = 0; f < NF; ++f)
-        __hip_atomic_fetch_add(&acc[f * ACC_HALF + ai], dH[f], __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(&acc[f * L::HALF + ai], dH[f], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 #pragma unroll
@@ -793,7 +807,7 @@ __device__ __forceinline__ void phase_xy(const StepArgs& s, const Phys<T>& ph, c
 // alternating registers instead of copying it back at every step: with the
 // 512-register budget that was 2-3 % faster in binary64 (the same bits); at
 // two wavefronts per SIMD it was 1 % slower.
-template <typename T, int NF, int MODE, int ZU>
+template <typename T, int NF, int MODE, int ZU, int AP>
 __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, const LeafInfo& li,
                                         const FaceNbr& fn, double* __restrict__ acc, int h,
                                         int lane, double dt, double inv_dx, bool& bad,
@@ -841,7 +855,8 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
     if (g.reg && (k == 5 || k == TW - 1)) record_face<T, NF>(g, fn, k - 5, x, y, H);
     if (kk >= 6) {
       const int i = k - 6;  // interior cell along z
-      const int ai = (i - k0) * ACC_PLANE + y * ACC_PITCH + x;
+      using L = AccLayout<AP>;
+      const int ai = (i - k0) * L::PLANE + y * L::PITCH + x;
       // rotating-frame sources of s_x, s_y, s_z, E from this cell's Uk
       double src[4] = {0.0, 0.0, 0.0, 0.0};
       const bool rot = g.omega != 0.0;
@@ -858,13 +873,13 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
       T cv[NF_CORE];
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        const double sum = acc[f * ACC_HALF + ai] + ((double)H[f] - Hprev[f]);
+        const double sum = acc[f * L::HALF + ai] + ((double)H[f] - Hprev[f]);
         const T o = finish_cell<T>(s, (size_t)f * fs, leaf_at + i * 64, st[f].qy, u0v[f], sum,
                                    rot && f >= 1 && f <= 4, f >= 1 && f <= 4 ? src[f - 1] : 0.0,
                                    dt, inv_dx);
         if (f < NF_CORE) cv[f] = o;
         if constexpr (MODE == STEP_RESTRICT) {
-          if (lnode >= 0) restrict_out<T>(s, &acc[f * ACC_HALF + ai], lnode, f, x, y, i, o);
+          if (lnode >= 0) restrict_out<T, L::PLANE>(s, &acc[f * L::HALF + ai], lnode, f, x, y, i, o);
         }
       }
       if constexpr (MODE == STEP_CFL) cflmin = fmin(cflmin, cfl_quantity<T>(g, cv, 1.0 / inv_dx));
@@ -881,7 +896,8 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
 // the registers its own work needs.
 template <typename T, int NF, int W, int MODE>
 __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
-  __shared__ __align__(16) double acc[NF * ACC_HALF];
+  constexpr int AP = W == 2 ? 8 : 9;  // accumulator row pitch (see AccLayout)
+  __shared__ __align__(16) double acc[NF * AccLayout<AP>::HALF];
   const GridArgs& g = s.g;
   const int leaf = s.leaf_base + leaf_of_block(blockIdx.x, g.n_leaves, s.remap);
   if (leaf >= g.n_leaves) return;
@@ -934,9 +950,10 @@ __global__ void __launch_bounds__(64, W) k_step(StepArgs s) {
   const int lnode = MODE == STEP_RESTRICT ? g.leaf_node[leaf] : -1;
 #pragma unroll 1
   for (int h = 0; h < 2; ++h) {
-    phase_xy<T, NF>(s, ph, li, fxy, acc, h, lane, bad);
+    phase_xy<T, NF, AP>(s, ph, li, fxy, acc, h, lane, bad);
     wave_lds_sync();
-    phase_z<T, NF, MODE, W == 1 ? 2 : 1>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad, cflmin, lnode);
+    phase_z<T, NF, MODE, W == 1 ? 2 : 1, AP>(s, ph, li, fz, acc, h, lane, dt, inv_dx, bad, cflmin,
+                                             lnode);
     wave_lds_sync();
   }
   if constexpr (MODE == STEP_CFL) atomic_min_positive(s.dt_next, cflmin, lane);
@@ -1189,7 +1206,7 @@ __device__ __forceinline__ void phase_z_group(const StepArgs& s, const Phys<T>& 
                                    fg >= 1 && fg <= 4 ? src[fg - 1] : 0.0, dt, inv_dx);
         if (F0 == 0 && f < NF_CORE) cv[f] = o;
         if constexpr (MODE == STEP_RESTRICT) {
-          if (lnode >= 0) restrict_out<T>(s, &acc[fg * ACC_HALF + ai], lnode, fg, x, y, i, o);
+          if (lnode >= 0) restrict_out<T, ACC_PLANE>(s, &acc[fg * ACC_HALF + ai], lnode, fg, x, y, i, o);
         }
       }
       if constexpr (MODE == STEP_CFL && F0 == 0)
