@@ -73,6 +73,13 @@ def hbm_bytes_per_leaf_stage(nf: int, w: int, with_u0: bool) -> int:
     return 512 * nf * w * (3 if with_u0 else 2)
 
 
+def fill_bytes_per_leaf(nf: int, w: int) -> int:
+    """Algorithmic HBM bytes of the ghost fill of one leaf: its 14^3 tile
+    written and its 8^3 cells read once (the neighbours' cells a tile reads
+    are other leaves' cells, counted with those leaves)."""
+    return (14 ** 3 + 512) * nf * w
+
+
 def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -483,7 +490,9 @@ def main():
                    "kernel": "k_step3d_ws<double,11> (3D reconstruction, 9-point Simpson flux, "
                              "one workgroup per leaf, each (cell, line) reconstructed once "
                              "per face orientation, x- and y-faces sharing their common lines)",
-                   "kernel_ms": kms3, "ghost_fill_ms": fill3, "ops_per_launch": ops3,
+                   "kernel_ms": kms3, "ghost_fill_ms": fill3,
+                   "ghost_fill_hbm_frac": fill_bytes_per_leaf(nf, 8) * n / (fill3 * 1e-3) / HBM_PEAK,
+                   "ops_per_launch": ops3,
                    "alu_frac": ops3 / (kms3 * 1e-3) / ALU_PEAK,
                    "hbm_frac": hbm_bytes_per_leaf_stage(nf, 8, True) * n / (kms3 * 1e-3) / HBM_PEAK}
         if not args.no_fp32:
@@ -491,7 +500,9 @@ def main():
             ms3f, kms3f, fill3f = time_rk3_3d(torch, hb, w, steps3, 1, hb.HYDRO_F32)
             recon3d["fp32_mixed"] = {
                 "value": cells / (ms3f * 1e-3), "ms_per_step": ms3f, "kernel_ms": kms3f,
-                "ghost_fill_ms": fill3f, "alu_frac": ops3 / (kms3f * 1e-3) / ALU_PEAK}
+                "ghost_fill_ms": fill3f,
+                "ghost_fill_hbm_frac": fill_bytes_per_leaf(nf, 4) * n / (fill3f * 1e-3) / HBM_PEAK,
+                "alu_frac": ops3 / (kms3f * 1e-3) / ALU_PEAK}
 
     # the method's optional terms on the same workload: coarse-fine flux
     # correction (recorded face fluxes + one k_reflux launch per face

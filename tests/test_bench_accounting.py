@@ -18,6 +18,12 @@ def test_axis_operation_count_per_leaf_and_substep():
     assert bench.ops_per_leaf_stage(6, True) == 3 * 64 * (355 * 6 + 9 * 80) + 512 * 6 * 11
 
 
+def test_ghost_fill_bytes_per_leaf():
+    # the 14^3 tile written and the leaf's own 8^3 cells read once, per field
+    assert bench.fill_bytes_per_leaf(11, 8) == (14 * 14 * 14 + 8 * 8 * 8) * 11 * 8 == 286_528
+    assert bench.fill_bytes_per_leaf(11, 4) * 2 == bench.fill_bytes_per_leaf(11, 8)
+
+
 def _distinct_cell_lines():
     """(cell, line direction) pairs whose PPM the 9-point face quadrature
     reads, over every face of one 8^3 leaf: face point (pu, pv) on side
