@@ -493,7 +493,8 @@ def main():
                              "one workgroup per leaf, each (cell, line) reconstructed once "
                              "per face orientation, x- and y-faces sharing their common lines)",
                    "kernel_ms": kms3, "ghost_fill_ms": fill3,
-                   "ghost_fill_hbm_frac": fill_bytes_per_leaf(nf, 8) * n / (fill3 * 1e-3) / HBM_PEAK,
+                   "ghost_fill_hbm_frac":
+                       fill_bytes_per_leaf(nf, 8) * n / (fill3 * 1e-3) / HBM_PEAK,
                    "ops_per_launch": ops3,
                    "alu_frac": ops3 / (kms3 * 1e-3) / ALU_PEAK,
                    "hbm_frac": hbm_bytes_per_leaf_stage(nf, 8, True) * n / (kms3 * 1e-3) / HBM_PEAK}

@@ -879,7 +879,8 @@ __device__ __forceinline__ void phase_z(const StepArgs& s, const Phys<T>& ph, co
                                    dt, inv_dx);
         if (f < NF_CORE) cv[f] = o;
         if constexpr (MODE == STEP_RESTRICT) {
-          if (lnode >= 0) restrict_out<T, L::PLANE>(s, &acc[f * L::HALF + ai], lnode, f, x, y, i, o);
+          if (lnode >= 0)
+            restrict_out<T, L::PLANE>(s, &acc[f * L::HALF + ai], lnode, f, x, y, i, o);
         }
       }
       if constexpr (MODE == STEP_CFL) cflmin = fmin(cflmin, cfl_quantity<T>(g, cv, 1.0 / inv_dx));
@@ -1206,7 +1207,8 @@ __device__ __forceinline__ void phase_z_group(const StepArgs& s, const Phys<T>& 
                                    fg >= 1 && fg <= 4 ? src[fg - 1] : 0.0, dt, inv_dx);
         if (F0 == 0 && f < NF_CORE) cv[f] = o;
         if constexpr (MODE == STEP_RESTRICT) {
-          if (lnode >= 0) restrict_out<T, ACC_PLANE>(s, &acc[fg * ACC_HALF + ai], lnode, fg, x, y, i, o);
+          if (lnode >= 0)
+            restrict_out<T, ACC_PLANE>(s, &acc[fg * ACC_HALF + ai], lnode, fg, x, y, i, o);
         }
       }
       if constexpr (MODE == STEP_CFL && F0 == 0)
